@@ -1,0 +1,20 @@
+"""MI355X-native evaluation and differentiation of sparse polynomial systems
+in complex double, double double and quad double arithmetic.
+
+The compute path is a HIP library with a C ABI (``include/polyeval.h``);
+``paper_1402_2626_amd.polyeval`` is its Python binding.  The binding is
+imported lazily so that the input generator (``synth``) can be used without
+loading the library.
+"""
+
+__all__ = ["synth", "polyeval"]
+
+
+def __getattr__(name):
+    if name == "polyeval":
+        from . import polyeval
+        return polyeval
+    if name == "synth":
+        from . import synth
+        return synth
+    raise AttributeError(name)

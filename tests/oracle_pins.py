@@ -1,0 +1,394 @@
+"""Checks that pin the CPU oracle to facts outside itself.
+
+Each ``pin_*`` function returns True when the oracle agrees with a closed form,
+an identity of the mathematics, or a library routine on a special case.  The
+pins are collected in ``ALL_PINS`` so that the mutation test can plant a
+mistake in the oracle and check that some pin fails.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+from paper_1402_2626_amd import synth
+
+
+def _exact_regime_value(re: int, im: int, a: int):
+    """(re + i im) * 2^a as an exact complex dyadic, and as a Python complex."""
+    return (re, im, a), complex(math.ldexp(re, a), math.ldexp(im, a))
+
+
+# ---------------------------------------------------------------- Speelpenning
+
+def pin_speelpenning_closed_form() -> bool:
+    """(1+i)^k and its gradient (1+i)^(k-1) in every slot, written in closed
+    form: (1+i)^2 = 2i, so (1+i)^(2m) = (2i)^m.  Section 2.2."""
+    one_plus_i = (1, 1, 0)
+    for k in (1, 2, 3, 4, 8, 9, 16):
+        v, g = O.speelpenning_straightforward([one_plus_i] * k)
+        want_v = (2j) ** (k // 2) * ((1 + 1j) if k % 2 else 1)
+        want_g = (2j) ** ((k - 1) // 2) * ((1 + 1j) if (k - 1) % 2 else 1)
+        if O.cdy_to_complex(v) != want_v:
+            return False
+        if any(O.cdy_to_complex(gi) != want_g for gi in g):
+            return False
+    return True
+
+
+def pin_speelpenning_figures() -> bool:
+    """The circuits of Fig. 1 (n = 4) and Fig. 2 (n = 8) compute the product and
+    every partial derivative; with distinct primes as inputs each partial is
+    the product divided by its own variable (integer division, exact)."""
+    for primes in ((2, 3, 5, 7), (2, 3, 5, 7, 11, 13, 17, 19)):
+        xs = [(p, 0, 0) for p in primes]
+        v, g = O.speelpenning_straightforward(xs)
+        P = math.prod(primes)
+        if O.cdy_to_complex(v) != P:
+            return False
+        if [O.cdy_to_complex(gi) for gi in g] != [P // p for p in primes]:
+            return False
+    return True
+
+
+def pin_speelpenning_euler() -> bool:
+    """For a product of distinct variables, x_i * dP/dx_i = P for every i:
+    checked exactly at a random unit-circle quad-double point."""
+    rng = synth.rng_for(11)
+    for k in (1, 2, 5, 16):
+        x = synth.unit_circle(rng, k, 4)
+        xs = O.point_from_limbs(x)
+        v, g = O.speelpenning_straightforward(xs)
+        for xi, gi in zip(xs, g):
+            d = O.cdy_add(O.cdy_mul(xi, gi), O.cdy_neg(v))
+            if not O.cdy_is_zero(d):
+                return False
+    return True
+
+
+# ---------------------------------------------------------------- linear systems
+
+def _linear_case(seed=3, N=7, n=5, L=2):
+    rng = synth.rng_for(seed)
+    C = rng.integers(-4, 5, size=(N, n)) + 1j * rng.integers(-4, 5, size=(N, n))
+    polys = []
+    for p in range(N):
+        polys.append([(C[p, j], [(j, 1)]) for j in range(n) if C[p, j] != 0])
+    sys_ = synth.from_monomial_lists(L, n, polys)
+    xs = synth.exact_regime_points(seed + 1, 1, n, L)[0]
+    xc = xs[0, 0] + 1j * xs[1, 0]
+    return sys_, xs, C, xc
+
+
+def pin_linear_system() -> bool:
+    """F = C x and J = C for a linear system (k = 1, d = 1), against numpy's
+    matrix-vector product on exactly representable data (non-square,
+    non-symmetric C, so a transposed index fails)."""
+    sys_, xs, C, xc = _linear_case()
+    F, J = O.eval_system(sys_, xs)
+    Fn = C @ xc
+    for p in range(C.shape[0]):
+        if O.cdy_to_complex(F[p]) != Fn[p]:
+            return False
+        for j in range(C.shape[1]):
+            got = O.cdy_to_complex(J[p].get(j, O.ZERO))
+            if got != C[p, j]:
+                return False
+    return True
+
+
+def pin_linear_adjoint() -> bool:
+    """J^H v = C^H v for a linear system, against numpy (exact data)."""
+    sys_, xs, C, xc = _linear_case(seed=5)
+    v = synth.exact_regime_points(9, 1, C.shape[0], sys_.level)[0]
+    vc = v[0, 0] + 1j * v[1, 0]
+    F, J = O.eval_system(sys_, xs)
+    g = O.adjoint_exact(J, O.point_from_limbs(v), sys_.n_vars)
+    want = C.conj().T @ vc
+    if [O.cdy_to_complex(gi) for gi in g] != list(want):
+        return False
+    cols = O.adjoint_columns(sys_, xs, v, range(sys_.n_vars))
+    return [O.cdy_to_complex(cols[j]) for j in range(sys_.n_vars)] == list(want)
+
+
+# ---------------------------------------------------------------- univariate
+
+def pin_univariate() -> bool:
+    """One variable: F = sum_d c_d x^d and J = sum_d d c_d x^(d-1), against
+    numpy.polynomial's polyval/polyder on exactly representable data."""
+    from numpy.polynomial import polynomial as npoly
+    rng = synth.rng_for(21)
+    for trial in range(6):
+        deg = int(rng.integers(1, 9))
+        coeffs = rng.integers(-5, 6, size=deg + 1) + 1j * rng.integers(-5, 6, size=deg + 1)
+        mons = [(coeffs[d], [(0, d)] if d else []) for d in range(deg + 1) if coeffs[d] != 0]
+        sys_ = synth.from_monomial_lists(2, 1, [mons])
+        x = synth.exact_regime_points(30 + trial, 1, 1, 2)[0]
+        xc = complex(x[0, 0, 0], x[1, 0, 0])
+        F, J = O.eval_system(sys_, x)
+        if O.cdy_to_complex(F[0]) != npoly.polyval(xc, coeffs):
+            return False
+        if O.cdy_to_complex(J[0].get(0, O.ZERO)) != npoly.polyval(xc, npoly.polyder(coeffs)):
+            return False
+    return True
+
+
+def pin_univariate_mpmath() -> bool:
+    """One variable at a full quad-double point: mpmath's polyval (with the
+    derivative) at 600 bits agrees with the exact oracle to 2^-500."""
+    import mpmath
+    rng = synth.rng_for(22)
+    deg = 7
+    coef = synth.unit_circle(rng, deg + 1, 4)
+    mons = [(0, [(0, d)] if d else []) for d in range(deg + 1)]
+    sys_ = synth.from_monomial_lists(4, 1, [mons], coef_limbs=coef)
+    x = synth.unit_circle(rng, 1, 4)
+    F, J = O.eval_system(sys_, x)
+    with mpmath.workprec(600):
+        cs = [mpmath.mpc(sum(mpmath.mpf(float(a)) for a in coef[0, :, d]),
+                         sum(mpmath.mpf(float(a)) for a in coef[1, :, d])) for d in range(deg + 1)]
+        xm = mpmath.mpc(sum(mpmath.mpf(float(a)) for a in x[0, :, 0]),
+                        sum(mpmath.mpf(float(a)) for a in x[1, :, 0]))
+        val, der = mpmath.polyval(cs[::-1], xm, derivative=True)
+        def close(a, b):
+            return abs(mpmath.mpc(mpmath.ldexp(a[0], a[2]), mpmath.ldexp(a[1], a[2])) - b) < mpmath.mpf(2) ** -500
+        return close(F[0], val) and close(J[0][0], der)
+
+
+# ---------------------------------------------------------------- quadratic form
+
+def pin_quadratic_form() -> bool:
+    """F = x^T A x (monomials x_i x_j, i < j, with coefficient A_ij + A_ji and
+    x_i^2 with A_ii) has J = x^T (A + A^T); against numpy on exact data."""
+    rng = synth.rng_for(31)
+    n = 6
+    A = rng.integers(-3, 4, size=(n, n)) + 1j * rng.integers(-3, 4, size=(n, n))
+    mons = []
+    for i in range(n):
+        if A[i, i] != 0:
+            mons.append((A[i, i], [(i, 2)]))
+        for j in range(i + 1, n):
+            c = A[i, j] + A[j, i]
+            if c != 0:
+                mons.append((c, [(i, 1), (j, 1)]))
+    sys_ = synth.from_monomial_lists(1, n, [mons])
+    x = synth.exact_regime_points(32, 1, n, 1)[0]
+    xc = x[0, 0] + 1j * x[1, 0]
+    F, J = O.eval_system(sys_, x)
+    if O.cdy_to_complex(F[0]) != xc @ A @ xc:
+        return False
+    want = xc @ (A + A.T)
+    return all(O.cdy_to_complex(J[0].get(j, O.ZERO)) == want[j] for j in range(n))
+
+
+# ---------------------------------------------------------------- finite differences
+
+def pin_finite_differences() -> bool:
+    """Central differences of the exact F with step h = 2^-80 along the real
+    and the imaginary axis of every variable match J to O(h^2); F is a
+    polynomial so the difference quotient is computed exactly."""
+    sys_ = synth.random_system(41, 4, n_vars=5, n_polys=3, m=4, k=3, exp_lo=1, exp_hi=4)
+    x = synth.unit_circle_points(synth.rng_for(42), 1, 5, 4)[0]
+    X = O.point_from_limbs(x)
+    F, J = O.eval_system(sys_, x)
+    h_exp = -80
+    for j in range(sys_.n_vars):
+        for direction in ((1, 0, h_exp), (0, 1, h_exp)):
+            Xp = list(X)
+            Xm = list(X)
+            Xp[j] = O.cdy_add(X[j], direction)
+            Xm[j] = O.cdy_add(X[j], O.cdy_neg(direction))
+            Fp = O.system_value_at(sys_, Xp)
+            Fm = O.system_value_at(sys_, Xm)
+            for p in range(sys_.n_polys):
+                diff = O.cdy_add(Fp[p], O.cdy_neg(Fm[p]))
+                # divide by 2h (times i for the imaginary step): exact
+                if direction[1]:
+                    diff = (diff[1], -diff[0], diff[2])
+                fd = (diff[0], diff[1], diff[2] - h_exp - 1)
+                err = O.cdy_abs_float(O.cdy_add(fd, O.cdy_neg(J[p].get(j, O.ZERO))))
+                if err > 1e-40:  # h^2 = 2^-160 ~ 7e-49 times moderate derivatives
+                    return False
+    return True
+
+
+# ---------------------------------------------------------------- homogeneity
+
+def _homogeneous_system(seed, L, n, N, m, D):
+    """Every monomial of polynomial p has total degree D (no constants)."""
+    rng = synth.rng_for(seed)
+    polys = []
+    for p in range(N):
+        mons = []
+        for t in range(m):
+            k = int(rng.integers(1, min(n, D) + 1))
+            vs = np.sort(rng.choice(n, size=k, replace=False))
+            ds = np.ones(k, dtype=int)
+            for _ in range(D - k):
+                ds[int(rng.integers(0, k))] += 1
+            mons.append((0, [(int(v), int(d)) for v, d in zip(vs, ds)]))
+        polys.append(mons)
+    M = N * m
+    coef = synth.unit_circle(rng, M, L)
+    return synth.from_monomial_lists(L, n, polys, coef_limbs=coef)
+
+
+def pin_euler_homogeneity() -> bool:
+    """Euler's identity for a homogeneous polynomial of degree D:
+    sum_j x_j J_pj = D F_p, checked exactly."""
+    D = 5
+    sys_ = _homogeneous_system(51, 2, n=6, N=3, m=5, D=D)
+    x = synth.unit_circle_points(synth.rng_for(52), 1, 6, 2)[0]
+    X = O.point_from_limbs(x)
+    F, J = O.eval_system(sys_, x)
+    for p in range(sys_.n_polys):
+        acc = O.ZERO
+        for j, v in J[p].items():
+            acc = O.cdy_add(acc, O.cdy_mul(X[j], v))
+        if not O.cdy_is_zero(O.cdy_add(acc, O.cdy_neg(O.cdy_scale(F[p], D)))):
+            return False
+    return True
+
+
+# ---------------------------------------------------------------- cyclic n-roots
+
+def pin_cyclic_at_one() -> bool:
+    """Cyclic n-roots (eq. (5)) at x = 1: F_i = n for the first n-1 equations
+    and 0 for the last; J_{i,m} = i (1-based i) and the last row is all ones."""
+    for n in (3, 4, 7):
+        sys_ = synth.cyclic_roots_system(n, 1)
+        if sys_.n_monomials != n * n - n + 2:
+            return False
+        x = np.zeros((2, 1, n))
+        x[0, 0] = 1.0
+        F, J = O.eval_system(sys_, x)
+        for i in range(n - 1):
+            if O.cdy_to_complex(F[i]) != n:
+                return False
+            if any(O.cdy_to_complex(J[i].get(j, O.ZERO)) != i + 1 for j in range(n)):
+                return False
+        if O.cdy_to_complex(F[n - 1]) != 0:
+            return False
+        if any(O.cdy_to_complex(J[n - 1].get(j, O.ZERO)) != 1 for j in range(n)):
+            return False
+    return True
+
+
+def pin_cyclic_at_roots_of_unity() -> bool:
+    """At x_j = w^j (w = e^{2 pi i/n}) the first n-1 equations vanish and the
+    last equals (-1)^(n-1) - 1; with x rounded to double double the oracle
+    must agree to 1e-28."""
+    import mpmath
+    for n in (5, 8):
+        sys_ = synth.cyclic_roots_system(n, 2)
+        x = np.zeros((2, 2, n))
+        with mpmath.workprec(300):
+            for j in range(n):
+                z = mpmath.expjpi(mpmath.mpf(2 * j) / n)
+                for part, val in ((0, z.real), (1, z.imag)):
+                    hi = float(val)
+                    lo = float(val - hi)
+                    x[part, 0, j], x[part, 1, j] = hi, lo
+        F, _ = O.eval_system(sys_, x, want_J=False)
+        for i in range(n - 1):
+            if O.cdy_abs_float(F[i]) > 1e-28 * n:
+                return False
+        want = (-1) ** (n - 1) - 1
+        if abs(O.cdy_to_complex(F[n - 1]) - want) > 1e-28 * n:
+            return False
+    return True
+
+
+# ---------------------------------------------------------------- limbs and metric
+
+def pin_limb_rounding() -> bool:
+    """Rounding exact values to limbs: known expansions, round-to-even ties,
+    and agreement with mpmath's own rounding to double of 1/3 and of the
+    remainders at 400 bits."""
+    import mpmath
+    v = O.cdy_add(O.cdy_add((1, 0, 0), (1, 0, -60)), O.cdy_add((1, 0, -120), (1, 0, -180)))
+    if list(O.cdy_to_limbs(v, 4)[0]) != [1.0, 2.0 ** -60, 2.0 ** -120, 2.0 ** -180]:
+        return False
+    tie = O.cdy_add((1, 0, 0), (1, 0, -53))  # halfway between 1 and 1 + 2^-52
+    if list(O.cdy_to_limbs(tie, 2)[0]) != [1.0, 2.0 ** -53]:
+        return False
+    third = ((1 << 400) // 3, 0, -400)
+    limbs = O.cdy_to_limbs(third, 4)[0]
+    with mpmath.workprec(400):
+        r = mpmath.ldexp(third[0], -400)
+        for l in range(4):
+            f = float(r)  # mpmath rounds to nearest
+            if f != limbs[l]:
+                return False
+            r -= f
+    return True
+
+
+def pin_abs_sums() -> bool:
+    """With unit-modulus coefficients and point entries in the exact regime
+    (|x| = 1 when a = 0), S_F(p) = number of monomials and S_J(p, j) = sum of
+    the exponents of x_j over polynomial p."""
+    sys_ = synth.random_system(61, 2, n_vars=6, n_polys=3, m=4, k=3, exp_lo=1, exp_hi=4)
+    sys_.coef[:] = 0.0
+    sys_.coef[0, 0] = 1.0
+    x = np.zeros((2, 2, 6))
+    x[1, 0] = 1.0  # x_j = i
+    SF, SJ = O.abs_sums_rows(sys_, x, range(3))
+    for p in range(3):
+        if SF[p] != 4.0:
+            return False
+        want = {}
+        for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+            vs, ds = sys_.monomial(t)
+            for v, d in zip(vs, ds):
+                want[int(v)] = want.get(int(v), 0) + int(d)
+        if {j: int(s) for j, s in SJ[p].items()} != want:
+            return False
+    return True
+
+
+# ---------------------------------------------------------------- Gauss-Newton
+
+def pin_gauss_newton_linear() -> bool:
+    """For F = C x - b (overdetermined), one Gauss-Newton step from any point
+    lands on the least-squares solution; against numpy.linalg.lstsq."""
+    rng = synth.rng_for(71)
+    N, n = 6, 3
+    C = rng.integers(-4, 5, size=(N, n)) + 1j * rng.integers(-4, 5, size=(N, n))
+    b = rng.integers(-4, 5, size=N) + 1j * rng.integers(-4, 5, size=N)
+    polys = [[(C[p, j], [(j, 1)]) for j in range(n) if C[p, j] != 0] + [(-b[p], [])] for p in range(N)]
+    sys_ = synth.from_monomial_lists(2, n, polys)
+    X0 = [(1, 0, 0)] * n
+    X1, _ = O.gauss_newton_step_mp(sys_, X0, prec=256)
+    want = np.linalg.lstsq(C, b, rcond=None)[0]
+    got = np.array([O.cdy_to_complex(v) for v in X1])
+    return bool(np.max(np.abs(got - want)) < 1e-12)
+
+
+def pin_gauss_newton_quadratic() -> bool:
+    """Planted root of a square random system (constant -F_p(x*) rounded to
+    quad double appended to each polynomial): from x* + 1e-3 noise the
+    distance to x* decays quadratically down to the rounding floor."""
+    sys_ = synth.random_system(81, 4, n_vars=4, n_polys=4, m=4, k=2, exp_lo=1, exp_hi=2)
+    xs = synth.unit_circle_points(synth.rng_for(82), 1, 4, 4)[0]
+    planted = O.plant_root(sys_, xs)
+    Xs = O.point_from_limbs(xs)
+    X = O.point_from_limbs(synth.perturbed_start(83, xs, 1e-3))
+    errs = []
+    for _ in range(6):
+        X, _ = O.gauss_newton_step_mp(planted, X, prec=512)
+        errs.append(max(O.cdy_abs_float(O.cdy_add(X[j], O.cdy_neg(Xs[j]))) for j in range(4)))
+    for a, b in zip(errs, errs[1:]):
+        if a > 1e-55 and b > 1e3 * a * a:
+            return False
+    return errs[-1] < 1e-58
+
+
+ALL_PINS = [
+    pin_speelpenning_closed_form, pin_speelpenning_figures, pin_speelpenning_euler,
+    pin_linear_system, pin_linear_adjoint, pin_univariate, pin_univariate_mpmath,
+    pin_quadratic_form, pin_finite_differences, pin_euler_homogeneity,
+    pin_cyclic_at_one, pin_cyclic_at_roots_of_unity, pin_limb_rounding, pin_abs_sums,
+    pin_gauss_newton_linear, pin_gauss_newton_quadratic,
+]

@@ -1,0 +1,186 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that at least
+one pin catches each of them."""
+import pytest
+
+import oracle.exact as E
+import oracle_pins as pins
+
+
+def _mut_power_off_by_one(v, d):
+    r = E.ONE
+    for _ in range(d + 1):
+        r = E.cdy_mul(r, v)
+    return r
+
+
+def _mut_mul_sign(a, b):
+    ar, ai, ae = a
+    br, bi, be = b
+    return (ar * br + ai * bi, ar * bi + ai * br, ae + be)
+
+
+def _mut_mul_swap(a, b):
+    ar, ai, ae = a
+    br, bi, be = b
+    return (ar * br - ai * bi, ar * bi - ai * br, ae + be)
+
+
+def _mut_add_shift(a, b):
+    ar, ai, ae = a
+    br, bi, be = b
+    if ae <= be:
+        s = be - ae
+        return (ar + (br << s), ai + (bi << s), ae)
+    s = ae - be
+    return ((ar << s) + br, (ai << s) + bi, ae)  # wrong exponent kept
+
+
+def _mut_partials_exponent_e(c, xs, ds):
+    k = len(xs)
+    pw = [E._power(xs[r], ds[r]) for r in range(k)]
+    value = c
+    for r in range(k):
+        value = E.cdy_mul(value, pw[r])
+    partials = []
+    for r in range(k):
+        g = E.cdy_scale(c, int(ds[r]) - 1)  # e = d - 1 instead of d
+        g = E.cdy_mul(g, E._power(xs[r], ds[r] - 1))
+        for s in range(k):
+            if s != r:
+                g = E.cdy_mul(g, pw[s])
+        partials.append(g)
+    return value, partials
+
+
+def _mut_partials_no_common_factor(c, xs, ds):
+    k = len(xs)
+    pw = [E._power(xs[r], ds[r]) for r in range(k)]
+    value = c
+    for r in range(k):
+        value = E.cdy_mul(value, pw[r])
+    partials = []
+    for r in range(k):
+        g = E.cdy_scale(c, int(ds[r]))
+        for s in range(k):
+            if s != r:
+                g = E.cdy_mul(g, pw[s])
+        partials.append(g)
+    return value, partials
+
+
+def _mut_partials_include_self(c, xs, ds):
+    k = len(xs)
+    pw = [E._power(xs[r], ds[r]) for r in range(k)]
+    value = c
+    for r in range(k):
+        value = E.cdy_mul(value, pw[r])
+    partials = []
+    for r in range(k):
+        g = E.cdy_scale(c, int(ds[r]))
+        g = E.cdy_mul(g, E._power(xs[r], ds[r] - 1))
+        for s in range(k):
+            g = E.cdy_mul(g, pw[s])  # forgot s != r
+        partials.append(g)
+    return value, partials
+
+
+def _mut_partials_dropped_last_factor(c, xs, ds):
+    k = len(xs)
+    pw = [E._power(xs[r], ds[r]) for r in range(k)]
+    value = c
+    for r in range(k):
+        value = E.cdy_mul(value, pw[r])
+    partials = []
+    for r in range(k):
+        g = E.cdy_scale(c, int(ds[r]))
+        g = E.cdy_mul(g, E._power(xs[r], ds[r] - 1))
+        for s in range(k - 1):
+            if s != r:
+                g = E.cdy_mul(g, pw[s])
+        partials.append(g)
+    return value, partials
+
+
+def _mut_conj_noop(a):
+    return a
+
+
+def _mut_from_limbs_drop_last(re_limbs, im_limbs):
+    re_limbs = list(re_limbs)[:-1] or [0.0]
+    im_limbs = list(im_limbs)[:-1] or [0.0]
+    r = (0, 0)
+    for f in re_limbs:
+        r = E._dy_add(r, E.dy_from_float(float(f)))
+    i = (0, 0)
+    for f in im_limbs:
+        i = E._dy_add(i, E.dy_from_float(float(f)))
+    e = min(r[1], i[1])
+    return (r[0] << (r[1] - e), i[0] << (i[1] - e), e)
+
+
+def _make_eval_rows_drop_last_monomial():
+    orig = E.eval_rows
+
+    def eval_rows(sys_, x, rows, want_J=True):
+        X = E.point_from_limbs(x)
+        F, J = {}, {}
+        for p in rows:
+            f = E.ZERO
+            jrow = {}
+            for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1]) - 1):
+                vs, ds = sys_.monomial(t)
+                value, partials = E.monomial_value_and_partials(E._coef(sys_, t), [X[v] for v in vs], ds)
+                f = E.cdy_add(f, value)
+                for r, v in enumerate(vs):
+                    v = int(v)
+                    jrow[v] = E.cdy_add(jrow[v], partials[r]) if v in jrow else partials[r]
+            F[p] = f
+            J[p] = jrow
+        return F, J
+    del orig
+    return eval_rows
+
+
+def _make_eval_rows_transposed():
+    orig = E.eval_rows
+
+    def eval_rows(sys_, x, rows, want_J=True):
+        F, J = orig(sys_, x, range(sys_.n_polys), want_J)
+        T = {p: {} for p in range(max(sys_.n_polys, sys_.n_vars))}
+        for p, row in J.items():
+            for j, v in row.items():
+                T.setdefault(j, {})[p] = v
+        return {p: F[p] for p in rows}, {p: T.get(p, {}) for p in rows}
+    return eval_rows
+
+
+MUTANTS = {
+    "power_off_by_one": ("_power", _mut_power_off_by_one),
+    "mul_sign": ("cdy_mul", _mut_mul_sign),
+    "mul_swapped_im": ("cdy_mul", _mut_mul_swap),
+    "add_exponent": ("cdy_add", _mut_add_shift),
+    "exponent_factor_e": ("monomial_value_and_partials", _mut_partials_exponent_e),
+    "no_common_factor": ("monomial_value_and_partials", _mut_partials_no_common_factor),
+    "partial_includes_self": ("monomial_value_and_partials", _mut_partials_include_self),
+    "partial_drops_factor": ("monomial_value_and_partials", _mut_partials_dropped_last_factor),
+    "adjoint_without_conj": ("cdy_conj", _mut_conj_noop),
+    "limbs_drop_last": ("cdy_from_limbs", _mut_from_limbs_drop_last),
+    "sum_drops_last_monomial": ("eval_rows", _make_eval_rows_drop_last_monomial()),
+    "J_transposed": ("eval_rows", _make_eval_rows_transposed()),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, monkeypatch):
+    attr, fn = MUTANTS[name]
+    monkeypatch.setattr(E, attr, fn)
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            ok = pin()
+        except Exception:
+            ok = False
+        if not ok:
+            failed.append(pin.__name__)
+            break
+    assert failed, f"mutant {name} passed every pin"
