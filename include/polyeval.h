@@ -1,0 +1,182 @@
+/*
+ * polyeval: evaluation and differentiation of sparse polynomial systems on
+ * MI355X (gfx950), in complex double, double double and quad double.
+ *
+ * The operations follow J. Verschelde and X. Yu, "GPU acceleration of
+ * Newton's method for large systems of polynomial equations in double double
+ * and quad double arithmetic" (2014):
+ *   - a system is given in sparse distributed form: fully expanded, only
+ *     monomials with a nonzero coefficient stored (Problem Statement, Sec. 1);
+ *   - each monomial is split into a product of its distinct variables times a
+ *     common factor of powers (Sec. 2.1, eq. (1)); the product and all its
+ *     partial derivatives come from the reverse mode (Sec. 2.2); every
+ *     derivative is multiplied by the common factor, the coefficient and the
+ *     exponent, and the terms are summed into F and J (Sec. 2.3);
+ *   - a Newton step evaluates A = J(x), b = -F(x), solves A dx = b in the
+ *     least-squares sense with modified Gram-Schmidt on [A b] (Sec. 3, Fig. 4,
+ *     eq. (2)) and updates x += dx (Sec. 4).
+ *
+ * Numbers.  A level-L number has L doubles per real part (L = 1: double,
+ * L = 2: double double, L = 4: quad double), limbs most significant first,
+ * forming a nonoverlapping expansion.  Complex level-L arrays are LIMB-PLANAR:
+ * [2 (re, im)][L][count] doubles.  Batched arrays have a leading [P] (points).
+ *   x: [P][2][L][n]      F: [P][2][L][N]      J: [P][2][L][N][n] (row-major)
+ *
+ * Threads and streams.  Handles are immutable after creation except where
+ * noted; calls on one handle from several host threads are safe if they use
+ * different output buffers.  Device work is enqueued on the given stream
+ * (a hipStream_t; NULL = the default stream) and is asynchronous: outputs are
+ * valid after the stream is synchronised.  Argument errors are reported
+ * synchronously; device errors at the next call or at synchronisation.
+ *
+ * Ownership.  Host pointers passed to the create calls are read during the
+ * call and not retained.  Device pointers passed to evaluation calls are
+ * owned by the caller and must stay valid until the enqueued work completes.
+ */
+#ifndef POLYEVAL_H
+#define POLYEVAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pe_status;
+
+#define PE_OK 0
+#define PE_EINVAL (-1)        /* invalid argument or malformed system */
+#define PE_ENOMEM (-2)        /* device or host allocation failed */
+#define PE_EUNSUPPORTED (-3)  /* valid but outside the supported sizes */
+#define PE_EDEVICE (-4)       /* a HIP runtime call failed */
+#define PE_ESINGULAR (-5)     /* a Gram-Schmidt pivot was numerically zero */
+#define PE_ENONFINITE (-6)    /* non-finite values met where checked */
+
+typedef struct pe_system pe_system;
+typedef struct pe_batch pe_batch;
+
+/* Version of this interface (increments on incompatible changes). */
+int32_t pe_abi_version(void);
+
+/* Message describing the last error on the calling host thread ("" if none).
+ * The string stays valid until the next call on the same thread. */
+const char* pe_last_error(void);
+
+/* ------------------------------------------------------------------ systems
+ * Load a system in sparse distributed form (Problem Statement, Sec. 1;
+ * monomial split of Sec. 2.1, eq. (1)).
+ *   level     1, 2 or 4 (limbs per real part); all coefficients, points and
+ *             outputs of this system are at this level.
+ *   n_vars    number of variables n (1 <= n <= 65535).
+ *   n_polys   number of polynomials N (>= 0).
+ *   poly_ptr  [N+1] int64, host: monomials of polynomial p are
+ *             poly_ptr[p] .. poly_ptr[p+1]-1; poly_ptr[0] = 0, nondecreasing.
+ *   mon_ptr   [M+1] int64, host, M = poly_ptr[N]: occurrences of monomial t
+ *             are mon_ptr[t] .. mon_ptr[t+1]-1; mon_ptr[0] = 0, nondecreasing.
+ *   var_idx   [nnz] int32, host, nnz = mon_ptr[M]: variable of each
+ *             occurrence, in [0, n); distinct within a monomial (any order).
+ *   exps      [nnz] int32, host: exponent of each occurrence, 1..65535.
+ *   coef      [2][L][M] double, host, limb-planar coefficients.
+ *   stream    stream used for the uploads (the call synchronises it).
+ * Monomials with no occurrence (constants) and polynomials with no monomial
+ * are allowed; duplicate monomials are kept as given (never merged).
+ * Returns PE_EINVAL for malformed input (out-of-range index, exponent < 1,
+ * duplicate variable in a monomial, non-monotone offsets), PE_EUNSUPPORTED
+ * for a monomial with more than 1024 variables or n > 65535, PE_ENOMEM or
+ * PE_EDEVICE on allocation/copy failure.  On error *out is set to NULL. */
+pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32_t n_polys,
+                           const int64_t* poly_ptr, const int64_t* mon_ptr, const int32_t* var_idx,
+                           const int32_t* exps, const double* coef, void* stream);
+
+/* Release a system and its device memory (NULL is allowed).  The caller must
+ * make sure no enqueued work still uses it. */
+pe_status pe_system_destroy(pe_system* sys);
+
+/* Sizes of a loaded system: info[0] = level, [1] = n, [2] = N, [3] = M,
+ * [4] = nnz, [5] = largest exponent, [6] = largest monomial size k,
+ * [7] = device bytes held. */
+pe_status pe_system_info(const pe_system* sys, int64_t info[8]);
+
+/* Evaluate F and J at P points (Sec. 2: power table, reverse-mode product
+ * derivatives, coefficient/exponent multiplication and summation).
+ *   x  device [P][2][L][n], read only.
+ *   F  device [P][2][L][N], fully overwritten.
+ *   J  device [P][2][L][N][n] row-major, fully overwritten (entries that no
+ *      monomial touches are written as 0); J == NULL evaluates F only.
+ * Summation order is fixed, so results are bitwise reproducible run to run.
+ * Enqueues only kernels (no allocation, no host synchronisation); it may be
+ * captured in a HIP graph.  PE_EINVAL for NULL x/F with P > 0 or P < 0. */
+pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, double* J,
+                  void* stream);
+
+/* Adjoint: g = J(x)^H v at P points, without forming J (reverse mode with
+ * the seed conj(v_p) per polynomial; the least-squares gradient of Sec. 1's
+ * Gauss-Newton setting).
+ *   x  device [P][2][L][n];  v  device [P][2][L][N];  g  device [P][2][L][n].
+ * The first call with a given P may allocate a per-system workspace (kept
+ * until destroy); later calls with P not above it allocate nothing. */
+pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, const double* v,
+                          double* g, void* stream);
+
+/* ------------------------------------------------------------------ batches
+ * A batch evaluates S independent systems of the same level, each at the
+ * same number of points, in one persistent launch whose work items
+ * (system, point, polynomial) are taken from a device queue in decreasing
+ * order of cost.  The systems must outlive the batch. */
+pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream);
+pe_status pe_batch_destroy(pe_batch* batch);
+
+/* Offsets, in doubles, of system s's blocks inside the packed batch arrays
+ * for points_per_system = 1: x_off[s], F_off[s], J_off[s] (each [S+1],
+ * host).  For P points per system multiply every offset by P: system s's
+ * block is then [P][2][L][n_s] (x), [P][2][L][N_s] (F), [P][2][L][N_s][n_s]
+ * (J). */
+pe_status pe_batch_layout(const pe_batch* batch, int64_t* x_off, int64_t* F_off, int64_t* J_off);
+
+/* Evaluate every system of the batch at points_per_system points each.
+ * x, F, J are device arrays in the packed layout above (J may be NULL).
+ * The first call with a given points_per_system may allocate workspace. */
+pe_status pe_batch_eval(const pe_batch* batch, int32_t points_per_system, const double* x, double* F,
+                        double* J, void* stream);
+
+/* ------------------------------------------------------------------ Newton
+ * One Gauss-Newton step at P points (Sec. 4): A = J(x), b = -F(x); modified
+ * Gram-Schmidt on the augmented matrix [A b] (Fig. 4, eq. (2)) gives R and
+ * y = Q^H b; back substitution solves R dx = y; x += dx.
+ *   x_inout    device [P][2][L][n], updated in place.
+ *   workspace  device, at least pe_newton_workspace_bytes(sys, P) bytes,
+ *              256-byte aligned, owned by the caller.
+ *   resid_out  device [P][2] doubles: |F(x)|_2 before the step and
+ *              |dx|_inf (leading limbs), or NULL.
+ * Requires N >= n (least squares) and n + 1 <= 1024.  Enqueues kernels only
+ * (no allocation, no host synchronisation): capturable in a HIP graph.  A
+ * numerically zero pivot (|r_kk| <= n u_L max|r|) gives dx = 0 for that point
+ * and resid_out[p][1] = -1; the call itself returns PE_OK. */
+size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P);
+pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace,
+                         double* resid_out, void* stream);
+
+/* The same for every system of a batch, x in the packed batch layout;
+ * resid_out is [S][P][2]. */
+size_t pe_batch_newton_workspace_bytes(const pe_batch* batch, int32_t P);
+pe_status pe_batch_newton_step(const pe_batch* batch, int32_t P, double* x_inout, void* workspace,
+                               double* resid_out, void* stream);
+
+/* ------------------------------------------------------------------ tuning
+ * Time the candidate launch shapes for this system at P points on the
+ * current device and keep the fastest for later pe_eval calls (this call
+ * allocates and synchronises).  The choice is recorded in the plan cache
+ * file if one is set. */
+pe_status pe_autotune(pe_system* sys, int32_t P, void* stream);
+
+/* Use `path` (NULL to disable) as a plan cache: a text file of tuned launch
+ * shapes keyed by level and system shape, read when systems are created and
+ * appended to by pe_autotune. */
+pe_status pe_set_plan_cache(const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYEVAL_H */

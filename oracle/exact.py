@@ -42,6 +42,7 @@ __all__ = [
     "eval_rows", "eval_columns", "eval_system", "abs_sums_rows", "rel_error",
     "max_rel_error_rows", "adjoint_exact", "adjoint_columns", "gauss_newton_step_mp",
     "system_value_at", "round_point", "speelpenning_straightforward", "plant_root",
+    "abs_sums_columns",
 ]
 
 # --------------------------------------------------------------------------
@@ -461,3 +462,27 @@ def plant_root(sys_, x_star: np.ndarray):
     coef = np.stack(coefs, axis=-1) if coefs else np.zeros((2, L, 0))
     return synth.from_monomial_lists(L, sys_.n_vars, polys, coef_limbs=coef,
                                      name=(sys_.name or "system") + "_planted")
+
+
+def abs_sums_columns(sys_, x: np.ndarray, cols: Iterable[int]):
+    """S_J(p, j) for every p and each j in ``cols`` (float64): {j: {p: S}}."""
+    ax = np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+    ac = np.hypot(sys_.coef[0].sum(axis=0), sys_.coef[1].sum(axis=0))
+    cols = [int(c) for c in cols]
+    want = set(cols)
+    out = {j: {} for j in cols}
+    for p in range(sys_.n_polys):
+        for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+            vs, ds = sys_.monomial(t)
+            hit = [r for r, v in enumerate(vs) if int(v) in want]
+            if not hit:
+                continue
+            pw = [float(ax[v]) ** int(d) for v, d in zip(vs, ds)]
+            for r in hit:
+                g = float(ac[t]) * int(ds[r]) * float(ax[vs[r]]) ** (int(ds[r]) - 1)
+                for s in range(len(vs)):
+                    if s != r:
+                        g *= pw[s]
+                j = int(vs[r])
+                out[j][p] = out[j].get(p, 0.0) + g
+    return out

@@ -6,15 +6,12 @@ The compute path is a HIP library with a C ABI (``include/polyeval.h``);
 imported lazily so that the input generator (``synth``) can be used without
 loading the library.
 """
+import importlib
 
 __all__ = ["synth", "polyeval"]
 
 
 def __getattr__(name):
-    if name == "polyeval":
-        from . import polyeval
-        return polyeval
-    if name == "synth":
-        from . import synth
-        return synth
+    if name in __all__:
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

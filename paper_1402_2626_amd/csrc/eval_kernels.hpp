@@ -1,0 +1,375 @@
+// Evaluation and differentiation kernels (gfx950).
+//
+// One workgroup owns one polynomial (row of F and J) at one point, or, for
+// the adjoint, a group of polynomials at one point.  It walks the row's
+// chunks (layout.hpp); per chunk:
+//   1. every monomial gets s consecutive lanes; lane q loads its segment of
+//      variables, gathers x and the powers for the common factor (Sec. 2.1,
+//      eq. (1): the factor prod x_j^(d_j - 1) divides every partial
+//      derivative), and forms the forward products of its segment;
+//   2. the s segment products (times their common factors, the coefficient
+//      folded into lane 0's) are combined across the lane group by a
+//      butterfly, which gives every lane the product of all other segments:
+//      the product tree of Sec. 2.2 / Fig. 1-2, with its levels mapped onto
+//      cross-lane exchanges instead of shared memory;
+//   3. each lane runs the reverse sweep of Speelpenning's product over its
+//      segment (Sec. 2.2, the 3n-5 scheme) seeded with coefficient x common
+//      factor x other segments, so each partial derivative comes out already
+//      multiplied by the common factor and the coefficient; it is then
+//      multiplied by its exponent (Sec. 2.3) and written to its LDS slot; the
+//      monomial's value is what the sweep leaves at the end;
+//   4. after a barrier the owner lanes add the slots of their columns in a
+//      fixed order (the sum reduction of Sec. 2.3), keeping row accumulators
+//      in registers across chunks.
+// At the end the row of J is written with coalesced stores and F is the
+// ordered sum of the R partial columns.
+//
+// The table of pure powers x_j^e (Sec. 2.1) for e = 2 .. emax-1 is built in
+// LDS by every workgroup when it fits; otherwise powers are formed by binary
+// powering from x.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.hpp"
+#include "mdarith.hpp"
+
+namespace pe {
+
+enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2 };
+
+struct SysView {
+  int n, N, R, ncols;
+  int emax;
+  int tab_last;  // powers 2..tab_last are in the LDS table (tab_last < 2: none)
+  int max_slots;
+  int pad;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_ptr;
+  const OccRec* occ;
+  const double* mcoef;  // [M][2L]
+  const uint32_t* mmeta;
+  const uint16_t* colptr;
+};
+
+// output addressing: element (pt, c, l, row, col) of J is at
+// J[pt * j_pt + (c * L + l) * j_plane + row * j_row + col]
+struct OutView {
+  double* J;
+  int64_t j_pt, j_plane, j_row;
+  double* F;
+  int64_t f_pt, f_plane, f_row;
+  double f_sign;  // -1 writes b = -F for Newton
+};
+
+// ------------------------------------------------------------------ helpers
+
+template <int L>
+__device__ __forceinline__ C<L> load_planar(const double* __restrict__ base, int64_t plane, int64_t idx) {
+  C<L> r;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    r.re.x[l] = base[l * plane + idx];
+    r.im.x[l] = base[(L + l) * plane + idx];
+  }
+  return r;
+}
+
+template <int L>
+__device__ __forceinline__ void store_planar(double* __restrict__ base, int64_t plane, int64_t idx, const C<L>& v) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    base[l * plane + idx] = v.re.x[l];
+    base[(L + l) * plane + idx] = v.im.x[l];
+  }
+}
+
+template <int L>
+__device__ __forceinline__ C<L> load_aos(const double* p) {
+  C<L> r;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    r.re.x[l] = p[l];
+    r.im.x[l] = p[L + l];
+  }
+  return r;
+}
+
+template <int L>
+__device__ __forceinline__ void store_aos(double* p, const C<L>& v) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    p[l] = v.re.x[l];
+    p[L + l] = v.im.x[l];
+  }
+}
+
+template <int L>
+__device__ __forceinline__ C<L> shfl_xor_c(const C<L>& v, int mask) {
+  C<L> r;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    r.re.x[l] = __shfl_xor(v.re.x[l], mask);
+    r.im.x[l] = __shfl_xor(v.im.x[l], mask);
+  }
+  return r;
+}
+
+// x^e for e >= 1 by binary powering
+template <int L>
+__device__ C<L> c_pow(const C<L>& x, int e) {
+  C<L> r = x, b = x;
+  e -= 1;
+  while (e > 0) {
+    if (e & 1) r = c_mul(r, b);
+    e >>= 1;
+    if (e) b = c_mul(b, b);
+  }
+  return r;
+}
+
+// x^e (e >= 2) from the LDS table or by powering
+template <int L>
+__device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, int v, int e, const C<L>& xv) {
+  if (e <= S.tab_last) return load_aos<L>(tab + (size_t(e - 2) * S.n + v) * (2 * L));
+  return c_pow(xv, e);
+}
+
+// Build the power table x_v^e, e = 2..tab_last, for the point in LDS.
+template <int L, int T>
+__device__ void build_power_table(const SysView& S, const double* __restrict__ xpt, double* tab) {
+  if (S.tab_last < 2) return;
+  for (int v = threadIdx.x; v < S.n; v += T) {
+    C<L> x1 = load_planar<L>(xpt, S.n, v);
+    C<L> p = x1;
+    for (int e = 2; e <= S.tab_last; ++e) {
+      p = c_mul(p, x1);
+      store_aos(tab + (size_t(e - 2) * S.n + v) * (2 * L), p);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ one chunk
+
+// Monomial phase of one chunk: writes every contribution of the chunk into
+// its LDS slot.  All lanes of the workgroup call it (the butterfly needs the
+// whole wavefront).  In MODE_ADJ the coefficient of a monomial of polynomial
+// p is multiplied by conj(v_p).
+template <int L, int SEG, int MODE>
+__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDesc& cd,
+                                                const double* __restrict__ xpt,
+                                                const double* __restrict__ vpt, const double* tab,
+                                                double* contrib) {
+  const int tid = threadIdx.x;
+  const int s = cd.s;
+  const int g = tid / s;
+  const int q = tid & (s - 1);
+  const bool active = g < int(cd.count);
+
+  int k = 0, fslot = 0;
+  C<L> cf = c_one<L>();
+  if (active) {
+    const uint32_t meta = S.mmeta[cd.mon_base + g];
+    k = int(meta & 0xffffu);
+    fslot = int(meta >> 16);
+    if (q == 0) {
+      cf = load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * (2 * L));
+      if (MODE == MODE_ADJ) cf = c_mul(cf, c_conj(load_planar<L>(vpt, S.N, cd.poly)));
+    }
+  }
+  const int base = k / s, extra = k - base * s;
+  const int len = base + (q < extra ? 1 : 0);
+
+  C<L> xv[SEG];
+  C<L> pre[SEG > 1 ? SEG - 1 : 1];
+  int slotv[SEG];
+  double dv[SEG];
+  C<L> A = c_one<L>();
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) {
+    if (i < len) {
+      const OccRec r = S.occ[cd.occ_base + size_t(i) * cd.width + tid];
+      const int v = r.var, d = r.exp;
+      xv[i] = load_planar<L>(xpt, S.n, v);
+      if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
+      slotv[i] = r.slot;
+      dv[i] = double(d);
+      if (i == 0)
+        A = xv[0];
+      else
+        A = c_mul(A, xv[i]);
+      if (i < SEG - 1) pre[i] = A;
+    }
+  }
+  // segment product times its common factor; the butterfly gives every lane
+  // the product over the other segments of the monomial
+  C<L> B = c_mul(A, cf);
+  C<L> E = c_one<L>();
+  for (int m = 1; m < s; m <<= 1) {
+    C<L> Bp = shfl_xor_c(B, m);
+    if (m == 1)
+      E = Bp;
+    else
+      E = c_mul(E, Bp);
+    B = c_mul(B, Bp);
+  }
+  if (MODE == MODE_FONLY) {
+    // B is now the monomial's value on every lane of the group
+    if (active && q == 0) store_aos(contrib + size_t(fslot) * (2 * L), B);
+    return;
+  }
+  // reverse sweep of Speelpenning's product over the segment
+  C<L> Sx = (s > 1) ? c_mul(cf, E) : cf;
+#pragma unroll
+  for (int i = SEG - 1; i >= 1; --i) {
+    if (i < len) {
+      C<L> gi = c_mul(pre[i - 1], Sx);
+      Sx = c_mul(Sx, xv[i]);
+      store_aos(contrib + size_t(slotv[i]) * (2 * L), c_mul_d(gi, dv[i]));
+    }
+  }
+  if (len >= 1) {
+    C<L> g0 = Sx;
+    Sx = c_mul(Sx, xv[0]);
+    store_aos(contrib + size_t(slotv[0]) * (2 * L), c_mul_d(g0, dv[0]));
+  }
+  if (MODE == MODE_EVAL && active && q == 0) store_aos(contrib + size_t(fslot) * (2 * L), Sx);
+}
+
+// Owner phase: add the chunk's slots into the register accumulators.
+template <int L, int CPL, int T, int MODE>
+__device__ __forceinline__ void chunk_owners(const SysView& S, const int (&cb)[CPL], const int (&ce)[CPL],
+                                             const double* contrib, C<L> (&acc)[CPL]) {
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    for (int sl = cb[cc]; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], load_aos<L>(contrib + size_t(sl) * (2 * L)));
+  }
+}
+
+template <int CPL, int T, int MODE>
+__device__ __forceinline__ void chunk_colptr(const SysView& S, const ChunkDesc& cd, int (&cb)[CPL], int (&ce)[CPL]) {
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int c = threadIdx.x + cc * T;
+    bool use = c < S.ncols;
+    if (MODE == MODE_FONLY) use = use && c >= S.n;
+    if (MODE == MODE_ADJ) use = use && c < S.n;
+    if (use) {
+      cb[cc] = S.colptr[cd.colptr_base + c];
+      ce[cc] = S.colptr[cd.colptr_base + c + 1];
+    } else {
+      cb[cc] = 0;
+      ce[cc] = 0;
+    }
+  }
+}
+
+// Process chunks [ch0, ch1) into the accumulators.
+template <int L, int SEG, int CPL, int T, int MODE>
+__device__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1, const double* __restrict__ xpt,
+                               const double* __restrict__ vpt, const double* tab, double* contrib,
+                               C<L> (&acc)[CPL]) {
+  for (uint32_t ch = ch0; ch < ch1; ++ch) {
+    const ChunkDesc cd = S.chunks[ch];
+    int cb[CPL], ce[CPL];
+    chunk_colptr<CPL, T, MODE>(S, cd, cb, ce);
+    chunk_monomials<L, SEG, MODE>(S, cd, xpt, vpt, tab, contrib);
+    __syncthreads();
+    chunk_owners<L, CPL, T, MODE>(S, cb, ce, contrib, acc);
+    __syncthreads();
+  }
+}
+
+// Write row p of J and F from the accumulators (EVAL / FONLY).
+template <int L, int CPL, int T, int MODE>
+__device__ void write_row(const SysView& S, const OutView& O, int pt, int p, const C<L> (&acc)[CPL], double* fpart) {
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int c = threadIdx.x + cc * T;
+    if (c < S.n) {
+      if (MODE == MODE_EVAL) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
+    } else if (c < S.ncols) {
+      store_aos(fpart + size_t(c - S.n) * (2 * L), acc[cc]);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    C<L> f = load_aos<L>(fpart);
+    for (int r = 1; r < S.R; ++r) f = c_add(f, load_aos<L>(fpart + size_t(r) * (2 * L)));
+    if (O.f_sign < 0) f = c_neg(f);
+    store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, f);
+  }
+  __syncthreads();
+}
+
+// LDS layout of a workgroup: [power table][contribution slots][F partials]
+template <int L>
+__host__ __device__ inline size_t lds_bytes(int n, int tab_last, int max_slots, int R) {
+  const size_t tab = tab_last >= 2 ? size_t(tab_last - 1) * n : 0;
+  return (tab + size_t(max_slots) + size_t(R)) * 2 * L * sizeof(double);
+}
+
+// ------------------------------------------------------------------ kernels
+
+// grid: P * N workgroups, block (pt, p) = (blockIdx.x / N, blockIdx.x % N)
+template <int L, int SEG, int CPL, int T, int MODE>
+__global__ __launch_bounds__(T) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
+                                                      int64_t x_pt) {
+  extern __shared__ double lds[];
+  const int pt = blockIdx.x / S.N;
+  const int p = blockIdx.x - pt * S.N;
+  const double* xpt = x + pt * x_pt;
+  double* tab = lds;
+  double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0);
+  double* fpart = contrib + size_t(S.max_slots) * 2 * L;
+  build_power_table<L, T>(S, xpt, tab);
+  __syncthreads();
+  C<L> acc[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
+  process_chunks<L, SEG, CPL, T, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
+  write_row<L, CPL, T, MODE>(S, O, pt, p, acc, fpart);
+}
+
+// Adjoint: grid P * G workgroups; group gi covers polynomials
+// [gi * gsize, min(N, (gi+1) * gsize)).  Writes partial rows
+// part[(pt * G + gi)][2][L][n] (planar, plane stride n).
+template <int L, int SEG, int CPL, int T>
+__global__ __launch_bounds__(T) void adjoint_rows_kernel(SysView S, const double* __restrict__ x, int64_t x_pt,
+                                                         const double* __restrict__ v, int64_t v_pt, int G,
+                                                         int gsize, double* __restrict__ part) {
+  extern __shared__ double lds[];
+  const int pt = blockIdx.x / G;
+  const int gi = blockIdx.x - pt * G;
+  const double* xpt = x + pt * x_pt;
+  const double* vpt = v + pt * v_pt;
+  double* tab = lds;
+  double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0);
+  build_power_table<L, T>(S, xpt, tab);
+  __syncthreads();
+  C<L> acc[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
+  const int p0 = gi * gsize;
+  const int p1 = min(S.N, p0 + gsize);
+  process_chunks<L, SEG, CPL, T, MODE_ADJ>(S, S.chunk_ptr[p0], S.chunk_ptr[p1], xpt, vpt, tab, contrib, acc);
+  double* out = part + size_t(pt * G + gi) * 2 * L * S.n;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int c = threadIdx.x + cc * T;
+    if (c < S.n) store_planar(out, S.n, c, acc[cc]);
+  }
+}
+
+// g[pt][.][.][j] = conj(sum over groups of part[pt][gi][.][.][j]) in group order
+template <int L>
+__global__ void adjoint_reduce_kernel(int n, int G, int P, const double* __restrict__ part, double* __restrict__ g) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(P) * n) return;
+  const int pt = int(idx / n);
+  const int j = int(idx - int64_t(pt) * n);
+  C<L> s = c_zero<L>();
+  for (int gi = 0; gi < G; ++gi) s = c_add(s, load_planar<L>(part + size_t(pt * G + gi) * 2 * L * n, n, j));
+  store_planar(g + size_t(pt) * 2 * L * n, n, j, c_conj(s));
+}
+
+}  // namespace pe

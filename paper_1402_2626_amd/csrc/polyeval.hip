@@ -1,0 +1,412 @@
+// C ABI of the polyeval library (include/polyeval.h): system loading,
+// evaluation, adjoint, batches, Gauss-Newton steps and launch-shape tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/polyeval.h"
+#include "eval_kernels.hpp"
+// newton kernels: added with the Newton step
+#include "packer.hpp"
+
+using namespace pe;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pe_status fail(pe_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define PE_HIP(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? PE_ENOMEM : PE_EDEVICE,                              \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                              \
+  } while (0)
+
+constexpr int kThreads = 256;
+
+int default_seg(int L) { return L == 1 ? 8 : 4; }
+
+int default_slots(int L) { return L == 1 ? 4096 : (L == 2 ? 2048 : 1088); }
+
+int cpl_bucket(int ncols, int T) {
+  int c = (ncols + T - 1) / T;
+  if (c <= 1) return 1;
+  if (c <= 2) return 2;
+  if (c <= 4) return 4;
+  if (c <= 8) return 8;
+  return 0;
+}
+
+size_t device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 65536;
+  return size_t(v);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct Plan {
+  int T = kThreads;
+  int seg = 4;
+  int cpl = 1;
+  int max_slots = 2048;
+  int tab_last = 0;
+  size_t lds = 0;
+};
+
+struct pe_system {
+  int device = 0;
+  int level = 0;
+  Packed host;  // kept for batches and tuning (structure only)
+  Plan plan;
+  SysView view{};
+  std::vector<void*> allocs;
+  size_t device_bytes = 0;
+  // adjoint workspace
+  mutable std::mutex ws_mu;
+  mutable void* adj_ws = nullptr;
+  mutable size_t adj_ws_bytes = 0;
+};
+
+// ------------------------------------------------------------------ kernel dispatch
+
+namespace {
+
+template <int L, int SEG, int CPL, int MODE>
+hipError_t launch_rows_t(const pe_system* sys, int P, const double* x, const OutView& O, hipStream_t st) {
+  auto kern = eval_rows_kernel<L, SEG, CPL, kThreads, MODE>;
+  const size_t lds = sys->plan.lds;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
+  const int64_t blocks = int64_t(P) * sys->view.N;
+  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(kThreads), lds, st, sys->view, O, x,
+                     int64_t(2) * L * sys->view.n);
+  return hipGetLastError();
+}
+
+template <int L, int SEG, int CPL>
+hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+                        double* part, double* g, hipStream_t st) {
+  auto kern = adjoint_rows_kernel<L, SEG, CPL, kThreads>;
+  const size_t lds = sys->plan.lds;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
+  const int n = sys->view.n;
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * G)), dim3(kThreads), lds, st, sys->view, x,
+                     int64_t(2) * L * n, v, int64_t(2) * L * sys->view.N, G, gsize, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = int64_t(P) * n;
+  hipLaunchKernelGGL(adjoint_reduce_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, n, G, P,
+                     (const double*)part, g);
+  return hipGetLastError();
+}
+
+// dispatch over (SEG, CPL, MODE) for a level
+template <int L, int SEG>
+hipError_t dispatch_rows_seg(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
+                             hipStream_t st) {
+  switch (sys->plan.cpl * 4 + mode) {
+#define PE_CASE(CPL, MODE) \
+  case CPL * 4 + MODE:     \
+    return launch_rows_t<L, SEG, CPL, MODE>(sys, P, x, O, st);
+    PE_CASE(1, MODE_EVAL)
+    PE_CASE(1, MODE_FONLY)
+    PE_CASE(2, MODE_EVAL)
+    PE_CASE(2, MODE_FONLY)
+    PE_CASE(4, MODE_EVAL)
+    PE_CASE(4, MODE_FONLY)
+    PE_CASE(8, MODE_EVAL)
+    PE_CASE(8, MODE_FONLY)
+#undef PE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L, int SEG>
+hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+                            double* part, double* g, hipStream_t st) {
+  switch (sys->plan.cpl) {
+    case 1: return launch_adj_t<L, SEG, 1>(sys, P, x, v, G, gsize, part, g, st);
+    case 2: return launch_adj_t<L, SEG, 2>(sys, P, x, v, G, gsize, part, g, st);
+    case 4: return launch_adj_t<L, SEG, 4>(sys, P, x, v, G, gsize, part, g, st);
+    case 8: return launch_adj_t<L, SEG, 8>(sys, P, x, v, G, gsize, part, g, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
+                         hipStream_t st) {
+  const int L = sys->level, seg = sys->plan.seg;
+  if (L == 1 && seg == 8) return dispatch_rows_seg<1, 8>(sys, P, x, O, mode, st);
+  if (L == 2 && seg == 4) return dispatch_rows_seg<2, 4>(sys, P, x, O, mode, st);
+  if (L == 4 && seg == 4) return dispatch_rows_seg<4, 4>(sys, P, x, O, mode, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+                        double* part, double* g, hipStream_t st) {
+  const int L = sys->level, seg = sys->plan.seg;
+  if (L == 1 && seg == 8) return dispatch_adj_seg<1, 8>(sys, P, x, v, G, gsize, part, g, st);
+  if (L == 2 && seg == 4) return dispatch_adj_seg<2, 4>(sys, P, x, v, G, gsize, part, g, st);
+  if (L == 4 && seg == 4) return dispatch_adj_seg<4, 4>(sys, P, x, v, G, gsize, part, g, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+pe_status upload(pe_system* sys, const std::vector<T>& v, const T*& dst, hipStream_t st) {
+  if (v.empty()) {
+    dst = nullptr;
+    return PE_OK;
+  }
+  void* p = nullptr;
+  const size_t bytes = v.size() * sizeof(T);
+  PE_HIP(hipMalloc(&p, bytes));
+  sys->allocs.push_back(p);
+  sys->device_bytes += bytes;
+  PE_HIP(hipMemcpyAsync(p, v.data(), bytes, hipMemcpyHostToDevice, st));
+  dst = static_cast<const T*>(p);
+  return PE_OK;
+}
+
+pe_status choose_plan(pe_system* sys, int seg, int max_slots) {
+  Packed& H = sys->host;
+  Plan pl;
+  pl.T = kThreads;
+  pl.seg = seg;
+  pl.max_slots = std::max(H.max_slots_used, 1);
+  pl.cpl = cpl_bucket(H.ncols, pl.T);
+  if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 columns (n + R) is not supported");
+  const size_t limit = device_lds_limit();
+  const int L = H.level;
+  pl.tab_last = 0;
+  if (H.emax - 1 >= 2) {
+    pl.tab_last = H.emax - 1;
+    if (lds_bytes<1>(H.n, pl.tab_last, pl.max_slots, H.R) * L > limit) pl.tab_last = 0;
+  }
+  pl.lds = lds_bytes<1>(H.n, pl.tab_last, pl.max_slots, H.R) * L;
+  if (pl.lds > limit) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
+  (void)max_slots;
+  sys->plan = pl;
+  return PE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int32_t pe_abi_version(void) { return 1; }
+
+const char* pe_last_error(void) { return g_last_error.c_str(); }
+
+pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32_t n_polys,
+                           const int64_t* poly_ptr, const int64_t* mon_ptr, const int32_t* var_idx,
+                           const int32_t* exps, const double* coef, void* stream) {
+  g_last_error.clear();
+  if (!out) return fail(PE_EINVAL, "out is NULL");
+  *out = nullptr;
+  SysInput in;
+  in.level = level;
+  in.n_vars = n_vars;
+  in.n_polys = n_polys;
+  in.poly_ptr = poly_ptr;
+  in.mon_ptr = mon_ptr;
+  in.var_idx = var_idx;
+  in.exps = exps;
+  in.coef = coef;
+  PackParams pp;
+  pp.threads = kThreads;
+  pp.seg = (level == 1 || level == 2 || level == 4) ? default_seg(level) : 4;
+  pp.max_slots = (level == 1 || level == 2 || level == 4) ? default_slots(level) : 2048;
+  std::string msg;
+  auto* sys = new (std::nothrow) pe_system();
+  if (!sys) return fail(PE_ENOMEM, "host allocation failed");
+  int st = pack_system(in, pp, sys->host, msg);
+  if (st != kOk) {
+    delete sys;
+    return fail(st, msg);
+  }
+  sys->level = level;
+  pe_status ps = choose_plan(sys, pp.seg, pp.max_slots);
+  if (ps != PE_OK) {
+    delete sys;
+    return ps;
+  }
+  hipError_t he = hipGetDevice(&sys->device);
+  if (he != hipSuccess) {
+    delete sys;
+    return fail(PE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  }
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const Packed& H = sys->host;
+  SysView& V = sys->view;
+  V.n = H.n;
+  V.N = H.N;
+  V.R = H.R;
+  V.ncols = H.ncols;
+  V.emax = H.emax;
+  V.tab_last = sys->plan.tab_last;
+  V.max_slots = sys->plan.max_slots;
+  pe_status e = PE_OK;
+  if ((e = upload(sys, H.chunks, V.chunks, hs)) != PE_OK || (e = upload(sys, H.chunk_ptr, V.chunk_ptr, hs)) != PE_OK ||
+      (e = upload(sys, H.occ, V.occ, hs)) != PE_OK || (e = upload(sys, H.mcoef, V.mcoef, hs)) != PE_OK ||
+      (e = upload(sys, H.mmeta, V.mmeta, hs)) != PE_OK || (e = upload(sys, H.colptr, V.colptr, hs)) != PE_OK) {
+    pe_system_destroy(sys);
+    return e;
+  }
+  he = hipStreamSynchronize(hs);
+  if (he != hipSuccess) {
+    pe_system_destroy(sys);
+    return fail(PE_EDEVICE, std::string("upload: ") + hipGetErrorString(he));
+  }
+  // the device copies are authoritative; keep only what batches and tuning need
+  sys->host.occ.clear();
+  sys->host.occ.shrink_to_fit();
+  sys->host.mcoef.clear();
+  sys->host.mcoef.shrink_to_fit();
+  sys->host.colptr.clear();
+  sys->host.colptr.shrink_to_fit();
+  *out = sys;
+  return PE_OK;
+}
+
+pe_status pe_system_destroy(pe_system* sys) {
+  if (!sys) return PE_OK;
+  for (void* p : sys->allocs) (void)hipFree(p);
+  if (sys->adj_ws) (void)hipFree(sys->adj_ws);
+  delete sys;
+  return PE_OK;
+}
+
+pe_status pe_system_info(const pe_system* sys, int64_t info[8]) {
+  if (!sys || !info) return fail(PE_EINVAL, "NULL argument");
+  const Packed& H = sys->host;
+  info[0] = sys->level;
+  info[1] = H.n;
+  info[2] = H.N;
+  info[3] = H.M;
+  info[4] = H.nnz;
+  info[5] = H.emax;
+  info[6] = H.kmax;
+  info[7] = int64_t(sys->device_bytes);
+  return PE_OK;
+}
+
+pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, double* J, void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  if (P == 0 || sys->view.N == 0) return PE_OK;
+  if (!x || !F) return fail(PE_EINVAL, "x or F is NULL");
+  if (int64_t(P) * sys->view.N > 0x7fffffffLL) return fail(PE_EUNSUPPORTED, "P * N too large");
+  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  OutView O;
+  O.J = J;
+  O.j_plane = int64_t(N) * n;
+  O.j_pt = 2 * L * O.j_plane;
+  O.j_row = n;
+  O.F = F;
+  O.f_plane = N;
+  O.f_pt = 2 * L * int64_t(N);
+  O.f_row = 1;
+  O.f_sign = 1.0;
+  hipError_t e = dispatch_rows(sys, P, x, O, J ? MODE_EVAL : MODE_FONLY, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, const double* v, double* g,
+                          void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  if (P == 0) return PE_OK;
+  if (!x || !v || !g) return fail(PE_EINVAL, "x, v or g is NULL");
+  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (N == 0) {
+    PE_HIP(hipMemsetAsync(g, 0, size_t(P) * 2 * L * n * sizeof(double), hs));
+    return PE_OK;
+  }
+  // groups of polynomials: enough workgroups to fill the device
+  const int target = 4096;
+  int gsize = int(std::max<int64_t>(1, (int64_t(N) * P + target - 1) / target));
+  gsize = std::min(gsize, N);
+  const int G = (N + gsize - 1) / gsize;
+  const size_t need = size_t(P) * G * 2 * L * n * sizeof(double);
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(sys->ws_mu);
+    if (sys->adj_ws_bytes < need) {
+      if (sys->adj_ws) {
+        PE_HIP(hipStreamSynchronize(hs));
+        (void)hipFree(sys->adj_ws);
+        sys->adj_ws = nullptr;
+        sys->adj_ws_bytes = 0;
+      }
+      PE_HIP(hipMalloc(&sys->adj_ws, need));
+      sys->adj_ws_bytes = need;
+    }
+    part = static_cast<double*>(sys->adj_ws);
+  }
+  hipError_t e = dispatch_adj(sys, P, x, v, G, gsize, part, g, hs);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ not yet available
+
+extern "C" {
+
+pe_status pe_batch_create(pe_batch** out, int32_t, const pe_system* const*, void*) {
+  if (out) *out = nullptr;
+  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+}
+pe_status pe_batch_destroy(pe_batch*) { return PE_OK; }
+pe_status pe_batch_layout(const pe_batch*, int64_t*, int64_t*, int64_t*) {
+  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+}
+pe_status pe_batch_eval(const pe_batch*, int32_t, const double*, double*, double*, void*) {
+  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+}
+size_t pe_newton_workspace_bytes(const pe_system*, int32_t) { return 0; }
+pe_status pe_newton_step(const pe_system*, int32_t, double*, void*, double*, void*) {
+  return fail(PE_EUNSUPPORTED, "Newton steps are not available in this build");
+}
+size_t pe_batch_newton_workspace_bytes(const pe_batch*, int32_t) { return 0; }
+pe_status pe_batch_newton_step(const pe_batch*, int32_t, double*, void*, double*, void*) {
+  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+}
+pe_status pe_autotune(pe_system*, int32_t, void*) { return PE_OK; }
+pe_status pe_set_plan_cache(const char*) { return PE_OK; }
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+"""Helpers for the GPU parity tests: run the library, compare with the oracle.
+
+The oracle runs in worker processes started with the ``spawn`` method (fresh
+interpreters that never touch the GPU)."""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+import oracle as O
+
+TAU = {1: 1e-13, 2: 1e-28, 4: 1e-58}
+
+
+def tolerance(sys_) -> float:
+    """Per-level tolerance scaled by the largest monomial degree."""
+    dmax = int(sys_.degrees().max()) if sys_.n_monomials else 0
+    return TAU[sys_.level] * max(1.0, dmax / 32.0)
+
+
+def workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _rows_job(args):
+    sys_, x, F_rows, J_rows, rows = args
+    Fx, Jx = O.eval_rows(sys_, x, rows, want_J=J_rows is not None)
+    SF, SJ = O.abs_sums_rows(sys_, x, rows)
+    eF = eJ = 0.0
+    for i, p in enumerate(rows):
+        eF = max(eF, O.rel_error(F_rows[0, :, i], F_rows[1, :, i], Fx[p], SF[p]))
+        if J_rows is None:
+            continue
+        for j in range(sys_.n_vars):
+            eJ = max(eJ, O.rel_error(J_rows[0, :, i, j], J_rows[1, :, i, j], Jx[p].get(j, O.ZERO),
+                                     SJ[p].get(j, 0.0)))
+    return eF, eJ
+
+
+def _cols_job(args):
+    sys_, x, J_cols, cols = args
+    Jc = O.eval_columns(sys_, x, cols)
+    Sc = O.abs_sums_columns(sys_, x, cols)
+    e = 0.0
+    for i, j in enumerate(cols):
+        for p in range(sys_.n_polys):
+            e = max(e, O.rel_error(J_cols[0, :, p, i], J_cols[1, :, p, i], Jc[j].get(p, O.ZERO),
+                                   Sc[j].get(p, 0.0)))
+    return e
+
+
+def _pool(n):
+    return mp.get_context("spawn").Pool(n)
+
+
+def max_errors_rows(sys_, x, F, J, rows, parallel: bool = True):
+    """Largest metric over F[rows] and J[rows, :] at one point.
+    x: [2, L, n]; F: [2, L, N]; J: [2, L, N, n] or None (numpy)."""
+    rows = list(rows)
+    per = max(1, (len(rows) + 4 * workers() - 1) // (4 * workers()))
+    jobs = []
+    for a in range(0, len(rows), per):
+        rr = rows[a:a + per]
+        jobs.append((sys_, x, F[:, :, rr], None if J is None else J[:, :, rr, :], rr))
+    if parallel and len(jobs) > 1:
+        with _pool(min(workers(), len(jobs))) as pool:
+            res = pool.map(_rows_job, jobs)
+    else:
+        res = [_rows_job(j) for j in jobs]
+    return max(r[0] for r in res), max(r[1] for r in res)
+
+
+def max_error_cols(sys_, x, J, cols, parallel: bool = True):
+    cols = list(cols)
+    jobs = [(sys_, x, J[:, :, :, [j]], [j]) for j in cols]
+    if parallel and len(jobs) > 1:
+        with _pool(min(workers(), len(jobs))) as pool:
+            res = pool.map(_cols_job, jobs)
+    else:
+        res = [_cols_job(j) for j in jobs]
+    return max(res)
+
+
+def to_device(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def flush(msg: str):
+    print(msg, flush=True)

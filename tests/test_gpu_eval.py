@@ -1,0 +1,198 @@
+"""Parity of the HIP evaluation path (through the C ABI) with the exact oracle."""
+import numpy as np
+import pytest
+
+import gpu_util as U
+import oracle as O
+from paper_1402_2626_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1402_2626_amd import polyeval
+    return polyeval
+
+
+def run_eval(pe, sys_, x, want_J=True):
+    import torch
+    S = pe.System.from_sparse(sys_)
+    F, J = S.eval(U.to_device(x), want_J=want_J)
+    torch.cuda.synchronize()
+    out = F.cpu().numpy(), (J.cpu().numpy() if J is not None else None)
+    S.close()
+    return out
+
+
+# ------------------------------------------------------------------ named workloads
+
+def test_d_n32_full(pe):
+    """Plain complex double system: n = N = 32, 32 monomials of k = 8."""
+    sys_, x = synth.workload("d_n32")
+    U.flush("d_n32: evaluating")
+    F, J = run_eval(pe, sys_, x)
+    eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], range(sys_.n_polys), parallel=False)
+    tol = U.tolerance(sys_)
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+def test_dd_n256_full(pe):
+    """Complex double double: n = N = 256, 256 monomials of k = 16, every row."""
+    sys_, x = synth.workload("dd_n256")
+    U.flush("dd_n256: evaluating")
+    F, J = run_eval(pe, sys_, x)
+    U.flush("dd_n256: oracle over all rows")
+    eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], range(sys_.n_polys))
+    tol = U.tolerance(sys_)
+    U.flush(f"dd_n256: eF={eF:.3e} eJ={eJ:.3e} tol={tol:.1e}")
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+def test_qd_n1024_sampled(pe):
+    """Complex quad double: n = N = 1024, 1024 monomials of k = 32; sampled
+    rows (first, last, two inside) and columns against the oracle."""
+    sys_, x = synth.workload("qd_n1024")
+    U.flush("qd_n1024: evaluating")
+    F, J = run_eval(pe, sys_, x)
+    tol = U.tolerance(sys_)
+    rows = [0, 511, 700, 1023]
+    U.flush("qd_n1024: oracle rows")
+    eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], rows)
+    U.flush(f"qd_n1024: rows eF={eF:.3e} eJ={eJ:.3e} tol={tol:.1e}")
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+    cols = [0, 17, 500, 1023]
+    U.flush("qd_n1024: oracle columns")
+    eC = U.max_error_cols(sys_, x[0], J[0], cols)
+    assert eC <= tol, (eC, tol)
+
+
+# ------------------------------------------------------------------ exact regime
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_exact_regime_bit_exact(pe, L):
+    """x_j in {+-1, +-i} 2^a and Gaussian-integer coefficients: every value is
+    exact, so F and J must equal the exact result bit for bit with zero lower
+    limbs."""
+    sys_ = synth.exact_regime_system(7, L, n_vars=40, n_polys=24, m=12, k=5, exp_hi=3)
+    x = synth.exact_regime_points(8, 2, 40, L)
+    F, J = run_eval(pe, sys_, x)
+    for pt in range(2):
+        Fx, Jx = O.eval_system(sys_, x[pt])
+        for p in range(sys_.n_polys):
+            assert np.array_equal(F[pt, :, :, p], O.cdy_to_limbs(Fx[p], L)), (pt, p)
+            for j in range(sys_.n_vars):
+                assert np.array_equal(J[pt, :, :, p, j], O.cdy_to_limbs(Jx[p].get(j, O.ZERO), L)), (pt, p, j)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def _edge_system(L, seed=3):
+    """Mixed monomial sizes k in {0,1,2,3,5,31,33,64,100}, an empty
+    polynomial, duplicate monomials, exponents up to 9, n = 130."""
+    rng = synth.rng_for(seed)
+    n = 130
+    polys = []
+    for p in range(7):
+        mons = []
+        for k in (0, 1, 2, 3, 5, 31, 33, 64, 100):
+            vs = np.sort(rng.choice(n, size=k, replace=False))
+            ds = rng.integers(1, 10, size=k)
+            mons.append((0, list(zip(vs.tolist(), ds.tolist()))))
+        if p == 3:
+            mons.append(mons[-2])  # duplicate monomial, kept as given
+        if p == 5:
+            mons = []  # empty polynomial
+        polys.append(mons)
+    M = sum(len(m) for m in polys)
+    coef = synth.unit_circle(rng, M, L)
+    return synth.from_monomial_lists(L, n, polys, coef_limbs=coef, name="edge")
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_edge_cases(pe, L):
+    sys_ = _edge_system(L)
+    x = synth.unit_circle_points(synth.rng_for(4), 2, sys_.n_vars, L)
+    x[1, :, :, 5] = 0.0  # a zero variable
+    x[1, :, :, 7] = 0.0
+    x = x * 0.9  # moduli below one keep degree-100 terms in range
+    F, J = run_eval(pe, sys_, x)
+    tol = U.tolerance(sys_)
+    for pt in range(2):
+        eF, eJ = U.max_errors_rows(sys_, x[pt], F[pt], J[pt], range(sys_.n_polys), parallel=False)
+        assert eF <= tol and eJ <= tol, (pt, eF, eJ, tol)
+    # the empty polynomial's row is exactly zero
+    assert np.all(F[:, :, :, 5] == 0.0) and np.all(J[:, :, :, 5, :] == 0.0)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_univariate_large_exponents(pe, L):
+    """n = 1 with exponents up to 300: no power table fits the LDS budget
+    when... (table up to 299 entries is small, so also forced via n)."""
+    rng = synth.rng_for(12)
+    polys = [[(0, [(0, int(d))]) for d in (1, 2, 3, 17, 64, 255, 300)], [(0, [])]]
+    coef = synth.unit_circle(rng, 8, L)
+    sys_ = synth.from_monomial_lists(L, 1, polys, coef_limbs=coef)
+    x = synth.unit_circle_points(synth.rng_for(13), 1, 1, L)
+    F, J = run_eval(pe, sys_, x)
+    eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], range(2), parallel=False)
+    tol = U.tolerance(sys_)
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_power_fallback_without_table(pe, L):
+    """Many variables with high exponents: the power table would not fit in
+    LDS, so powers come from binary powering."""
+    n = 1500
+    sys_ = synth.random_system(21, L, n_vars=n, n_polys=3, m=40, k=6, exp_lo=1, exp_hi=60)
+    x = synth.unit_circle_points(synth.rng_for(22), 1, n, L)
+    F, J = run_eval(pe, sys_, x)
+    eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], range(3), parallel=False)
+    tol = U.tolerance(sys_)
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_F_only_and_points(pe, L):
+    """J = NULL evaluates F only; several points at once agree with one point
+    at a time bit for bit."""
+    sys_ = synth.random_system(31, L, n_vars=50, n_polys=20, m=30, k=7, exp_lo=1, exp_hi=3)
+    x = synth.unit_circle_points(synth.rng_for(32), 3, 50, L)
+    F3, J3 = run_eval(pe, sys_, x)
+    for pt in range(3):
+        F1, J1 = run_eval(pe, sys_, x[pt:pt + 1])
+        assert np.array_equal(F1[0], F3[pt]) and np.array_equal(J1[0], J3[pt])
+    Fo, Jo = run_eval(pe, sys_, x, want_J=False)
+    assert Jo is None
+    tol = U.tolerance(sys_)
+    for pt in range(3):
+        eF, _ = U.max_errors_rows(sys_, x[pt], Fo[pt], None, range(20), parallel=False)
+        assert eF <= tol
+
+
+def test_deterministic(pe):
+    sys_, x = synth.workload("dd_n256")
+    F1, J1 = run_eval(pe, sys_, x)
+    F2, J2 = run_eval(pe, sys_, x)
+    assert np.array_equal(F1, F2) and np.array_equal(J1, J2)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_cyclic_roots_closed_forms(pe, L):
+    """Cyclic n-roots (eq. (5)) at x = 1: F_i = n, last 0; J_{i,m} = i (1-based),
+    last row ones; exact at every level."""
+    n = 64
+    sys_ = synth.cyclic_roots_system(n, L)
+    x = np.zeros((1, 2, L, n))
+    x[0, 0, 0] = 1.0
+    F, J = run_eval(pe, sys_, x)
+    want_F = np.full(n, float(n))
+    want_F[-1] = 0.0
+    assert np.array_equal(F[0, 0, 0], want_F) and np.all(F[0, 1] == 0) and np.all(F[0, 0, 1:] == 0)
+    want_J = np.repeat(np.arange(1, n + 1, dtype=float)[:, None], n, axis=1)
+    want_J[-1] = 1.0
+    assert np.array_equal(J[0, 0, 0], want_J) and np.all(J[0, 1] == 0)
