@@ -1,0 +1,174 @@
+// Gauss-Newton step on the device: modified Gram-Schmidt on the augmented
+// matrix [A b] with A = J(x), b = -F(x) (Sec. 3, Fig. 4 and eq. (2)), back
+// substitution R dx = y, and the update x += dx (Sec. 4).
+//
+// One workgroup per (system, point); thread j owns columns j, j + T, ... of
+// [A b].  Column k (the pivot) is staged in LDS at step k.  As in the paper's
+// delayed normalisation, the pivot column is never normalised in memory: the
+// projection coefficient of column j is (a_k^H a_j) / |a_k|^2 and
+// r_kj = (a_k^H a_j) / |a_k|, which is all the least-squares solve needs
+// (Q itself is not returned).  The squared norm of the next pivot is
+// accumulated by its owner while it updates that column.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "eval_kernels.hpp"
+#include "mdarith.hpp"
+
+namespace pe {
+
+constexpr int kMgsThreads = 256;
+
+template <int L>
+__device__ __forceinline__ R<L> r_load_aos(const double* p) {
+  R<L> r;
+#pragma unroll
+  for (int l = 0; l < L; ++l) r.x[l] = p[l];
+  return r;
+}
+
+template <int L>
+__device__ __forceinline__ void r_store_aos(double* p, const R<L>& v) {
+#pragma unroll
+  for (int l = 0; l < L; ++l) p[l] = v.x[l];
+}
+
+template <int L>
+__device__ __forceinline__ C<L> c_mul_conj_a(const C<L>& a, const C<L>& b) {
+  return c_mul(c_conj(a), b);
+}
+
+// Per point: A (planar [2][L][N][ld], ld = n + 1, column n = b) is
+// overwritten; Rw gets R as [n][n+1] complex AoS (diagonal real); yw is
+// [n] complex AoS scratch for the back substitution; x is updated.
+template <int L, int T>
+__global__ __launch_bounds__(T) void mgs_solve_kernel(int N, int n, double* __restrict__ W, int64_t w_pt,
+                                                      double* __restrict__ Rw, int64_t r_pt,
+                                                      double* __restrict__ yw, int64_t y_pt,
+                                                      double* __restrict__ X, int64_t x_pt,
+                                                      double* __restrict__ resid) {
+  extern __shared__ double lds[];
+  const int pt = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ld = n + 1;
+  const int64_t plane = int64_t(N) * ld;
+  double* A = W + pt * w_pt;
+  double* Rm = Rw + pt * r_pt;
+  double* Y = yw + pt * y_pt;
+  double* colk = lds;                             // N complex, AoS
+  double* sh = colk + size_t(N) * 2 * L;          // [0..L): |a_k|^2 of the next pivot
+  double* red = sh + 2 * L;                       // T doubles for reductions
+  int* flag = reinterpret_cast<int*>(red + T);    // singular flag
+
+  // |F|_2 from the leading limbs of b = -F
+  double fs = 0.0;
+  for (int i = tid; i < N; i += T) {
+    const double re = A[0 * plane + int64_t(i) * ld + n];
+    const double im = A[int64_t(L) * plane + int64_t(i) * ld + n];
+    fs += re * re + im * im;
+  }
+  red[tid] = fs;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int s = T / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double fnorm = sqrt(red[0]);
+  __syncthreads();
+
+  // squared norm of column 0
+  if (tid == 0) {
+    R<L> s2 = r_zero<L>();
+    for (int i = 0; i < N; ++i) s2 = r_add(s2, c_norm2(load_planar<L>(A, plane, int64_t(i) * ld)));
+    r_store_aos(sh, s2);
+  }
+  double rmax = 0.0;
+  const double uL = (L == 1) ? 0x1p-53 : (L == 2 ? 0x1p-104 : 0x1p-206);
+
+  for (int k = 0; k < n; ++k) {
+    for (int i = tid; i < N; i += T) store_aos(colk + size_t(i) * 2 * L, load_planar<L>(A, plane, int64_t(i) * ld + k));
+    __syncthreads();
+    const R<L> nk = r_load_aos<L>(sh);
+    const R<L> rkk = r_sqrt(nk);
+    rmax = fmax(rmax, rkk.x[0]);
+    if (!(rkk.x[0] > double(n) * uL * rmax)) {
+      if (tid == 0) *flag = 1;
+      break;  // uniform: every thread reads the same values
+    }
+    const R<L> inv_n = r_recip(nk);
+    const R<L> inv_r = r_recip(rkk);
+    if (tid == 0) {
+      C<L> d;
+      d.re = rkk;
+      d.im = r_zero<L>();
+      store_aos(Rm + (size_t(k) * ld + k) * 2 * L, d);
+    }
+    __syncthreads();  // everyone has read sh before it is overwritten below
+    for (int j = k + 1 + tid; j <= n; j += T) {
+      C<L> dot = c_zero<L>();
+      for (int i = 0; i < N; ++i)
+        dot = c_add(dot, c_mul_conj_a(load_aos<L>(colk + size_t(i) * 2 * L), load_planar<L>(A, plane, int64_t(i) * ld + j)));
+      store_aos(Rm + (size_t(k) * ld + j) * 2 * L, c_mul_r(dot, inv_r));
+      const C<L> cr = c_neg(c_mul_r(dot, inv_n));
+      const bool next = (j == k + 1);
+      R<L> s2 = r_zero<L>();
+      for (int i = 0; i < N; ++i) {
+        C<L> a = load_planar<L>(A, plane, int64_t(i) * ld + j);
+        a = c_add(a, c_mul(cr, load_aos<L>(colk + size_t(i) * 2 * L)));
+        store_planar(A, plane, int64_t(i) * ld + j, a);
+        if (next) s2 = r_add(s2, c_norm2(a));
+      }
+      if (next) r_store_aos(sh, s2);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool singular = *flag != 0;
+
+  // back substitution R dx = y, y = column n of R; dx overwrites Y
+  if (!singular) {
+    for (int i = tid; i < n; i += T) store_aos(Y + size_t(i) * 2 * L, load_aos<L>(Rm + (size_t(i) * ld + n) * 2 * L));
+    __syncthreads();
+    for (int k = n - 1; k >= 0; --k) {
+      if (tid == 0) {
+        const R<L> rkk = load_aos<L>(Rm + (size_t(k) * ld + k) * 2 * L).re;
+        store_aos(Y + size_t(k) * 2 * L, c_mul_r(load_aos<L>(Y + size_t(k) * 2 * L), r_recip(rkk)));
+      }
+      __syncthreads();
+      const C<L> dk = load_aos<L>(Y + size_t(k) * 2 * L);
+      for (int i = tid; i < k; i += T) {
+        const C<L> t = c_mul(load_aos<L>(Rm + (size_t(i) * ld + k) * 2 * L), dk);
+        store_aos(Y + size_t(i) * 2 * L, c_sub(load_aos<L>(Y + size_t(i) * 2 * L), t));
+      }
+      __syncthreads();
+    }
+  }
+  // update x and the step size
+  double dmax = 0.0;
+  double* xp = X + pt * x_pt;
+  for (int j = tid; j < n; j += T) {
+    if (!singular) {
+      const C<L> d = load_aos<L>(Y + size_t(j) * 2 * L);
+      store_planar(xp, n, j, c_add(load_planar<L>(xp, n, j), d));
+      dmax = fmax(dmax, fmax(fabs(d.re.x[0]), fabs(d.im.x[0])));
+    }
+  }
+  red[tid] = dmax;
+  __syncthreads();
+  for (int s = T / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0 && resid) {
+    resid[2 * pt] = fnorm;
+    resid[2 * pt + 1] = singular ? -1.0 : red[0];
+  }
+}
+
+template <int L>
+__host__ __device__ inline size_t mgs_lds_bytes(int N) {
+  return size_t(N) * 2 * L * sizeof(double) + 2 * L * sizeof(double) + kMgsThreads * sizeof(double) + 16;
+}
+
+}  // namespace pe

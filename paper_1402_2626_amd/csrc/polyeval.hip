@@ -14,7 +14,7 @@
 
 #include "../../include/polyeval.h"
 #include "eval_kernels.hpp"
-// newton kernels: added with the Newton step
+#include "newton_kernels.hpp"
 #include "packer.hpp"
 
 using namespace pe;
@@ -383,6 +383,98 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ Newton
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct NewtonLayout {
+  size_t w_off, r_off, y_off, total;
+  int64_t w_pt, r_pt, y_pt;  // in doubles
+};
+
+NewtonLayout newton_layout(int L, int N, int n, int P) {
+  NewtonLayout lo;
+  lo.w_pt = int64_t(2) * L * N * (n + 1);
+  lo.r_pt = int64_t(n) * (n + 1) * 2 * L;
+  lo.y_pt = int64_t(n) * 2 * L;
+  lo.w_off = 0;
+  lo.r_off = align256(lo.w_off + size_t(P) * lo.w_pt * sizeof(double));
+  lo.y_off = align256(lo.r_off + size_t(P) * lo.r_pt * sizeof(double));
+  lo.total = align256(lo.y_off + size_t(P) * lo.y_pt * sizeof(double));
+  return lo;
+}
+
+template <int L>
+hipError_t launch_mgs(int P, int N, int n, double* W, const NewtonLayout& lo, char* base, double* x,
+                      double* resid, hipStream_t st) {
+  auto kern = mgs_solve_kernel<L, kMgsThreads>;
+  const size_t lds = mgs_lds_bytes<L>(N);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(unsigned(P)), dim3(kMgsThreads), lds, st, N, n, W, lo.w_pt,
+                     reinterpret_cast<double*>(base + lo.r_off), lo.r_pt, reinterpret_cast<double*>(base + lo.y_off),
+                     lo.y_pt, x, int64_t(2) * L * n, resid);
+  return hipGetLastError();
+}
+
+pe_status newton_check(const pe_system* sys, int P) {
+  const int n = sys->view.n, N = sys->view.N;
+  if (N < n) return fail(PE_EUNSUPPORTED, "Gauss-Newton needs at least as many polynomials as variables");
+  if (n + 1 > 1024) return fail(PE_EUNSUPPORTED, "Gauss-Newton supports n + 1 <= 1024");
+  const int L = sys->level;
+  const size_t lds = L == 1 ? mgs_lds_bytes<1>(N) : (L == 2 ? mgs_lds_bytes<2>(N) : mgs_lds_bytes<4>(N));
+  if (lds > device_lds_limit()) return fail(PE_EUNSUPPORTED, "too many polynomials for the LDS pivot column");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  return PE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P) {
+  if (!sys || P < 0) return 0;
+  return newton_layout(sys->level, sys->view.N, sys->view.n, P).total;
+}
+
+pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace, double* resid_out,
+                         void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  pe_status ps = newton_check(sys, P);
+  if (ps != PE_OK) return ps;
+  if (P == 0) return PE_OK;
+  if (!x_inout || !workspace) return fail(PE_EINVAL, "x or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
+  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  const NewtonLayout lo = newton_layout(L, N, n, P);
+  char* base = static_cast<char*>(workspace);
+  double* W = reinterpret_cast<double*>(base + lo.w_off);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  OutView O;
+  O.J = W;
+  O.j_row = n + 1;
+  O.j_plane = int64_t(N) * (n + 1);
+  O.j_pt = lo.w_pt;
+  O.F = W + n;
+  O.f_row = n + 1;
+  O.f_plane = O.j_plane;
+  O.f_pt = lo.w_pt;
+  O.f_sign = -1.0;
+  hipError_t e = dispatch_rows(sys, P, x_inout, O, MODE_EVAL, hs);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton eval launch: ") + hipGetErrorString(e));
+  if (L == 1) e = launch_mgs<1>(P, N, n, W, lo, base, x_inout, resid_out, hs);
+  if (L == 2) e = launch_mgs<2>(P, N, n, W, lo, base, x_inout, resid_out, hs);
+  if (L == 4) e = launch_mgs<4>(P, N, n, W, lo, base, x_inout, resid_out, hs);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton solve launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------------ not yet available
 
 extern "C" {
@@ -397,10 +489,6 @@ pe_status pe_batch_layout(const pe_batch*, int64_t*, int64_t*, int64_t*) {
 }
 pe_status pe_batch_eval(const pe_batch*, int32_t, const double*, double*, double*, void*) {
   return fail(PE_EUNSUPPORTED, "batches are not available in this build");
-}
-size_t pe_newton_workspace_bytes(const pe_system*, int32_t) { return 0; }
-pe_status pe_newton_step(const pe_system*, int32_t, double*, void*, double*, void*) {
-  return fail(PE_EUNSUPPORTED, "Newton steps are not available in this build");
 }
 size_t pe_batch_newton_workspace_bytes(const pe_batch*, int32_t) { return 0; }
 pe_status pe_batch_newton_step(const pe_batch*, int32_t, double*, void*, double*, void*) {
