@@ -372,4 +372,82 @@ __global__ void adjoint_reduce_kernel(int n, int G, int P, const double* __restr
   store_planar(g + size_t(pt) * 2 * L * n, n, j, c_conj(s));
 }
 
+// ------------------------------------------------------------------ batches
+
+// Outputs of a batch: system s's F/J blocks start at P * F_off[s] and
+// P * J_off[s] (doubles).  In Newton mode J points at the workspace of
+// augmented matrices [J | -F] (row stride n + 1) and F is unused.
+struct BatchOut {
+  double* J;
+  const int64_t* J_off;
+  double* F;
+  const int64_t* F_off;
+  int newton;
+};
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// Persistent kernel: workgroups take (system, polynomial) items from a
+// device counter in the order of `items` (decreasing cost) until none is
+// left; each item is evaluated at all P points.  Every workgroup reaches the
+// exit test after every item, so the grid drains.
+template <int L, int SEG, int CPL, int T, int MODE>
+__global__ __launch_bounds__(T) void batch_rows_kernel(const SysView* __restrict__ views,
+                                                       const uint64_t* __restrict__ items, int64_t nitems,
+                                                       int* counter, int P, const double* __restrict__ x,
+                                                       const int64_t* __restrict__ x_off, BatchOut out) {
+  extern __shared__ double lds[];
+  __shared__ int64_t item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int64_t it = item_sh;
+    __syncthreads();
+    if (it >= nitems) break;
+    const uint64_t w = items[it];
+    const int s = int(w >> 32);
+    const int p = int(w & 0xffffffffu);
+    const SysView S = views[s];
+    const int n = S.n, N = S.N;
+    OutView O;
+    if (out.newton) {
+      const int64_t ld = n + 1;
+      O.J = out.J + out.J_off[s] * P;
+      O.j_row = ld;
+      O.j_plane = int64_t(N) * ld;
+      O.j_pt = 2 * L * O.j_plane;
+      O.F = O.J + n;
+      O.f_row = ld;
+      O.f_plane = O.j_plane;
+      O.f_pt = O.j_pt;
+      O.f_sign = -1.0;
+    } else {
+      O.J = out.J ? out.J + out.J_off[s] * P : nullptr;
+      O.j_row = n;
+      O.j_plane = int64_t(N) * n;
+      O.j_pt = 2 * L * O.j_plane;
+      O.F = out.F + out.F_off[s] * P;
+      O.f_row = 1;
+      O.f_plane = N;
+      O.f_pt = 2 * L * int64_t(N);
+      O.f_sign = 1.0;
+    }
+    double* tab = lds;
+    double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * n * 2 * L : 0);
+    double* fpart = contrib + size_t(S.max_slots) * 2 * L;
+    for (int pt = 0; pt < P; ++pt) {
+      const double* xpt = x + x_off[s] * P + int64_t(pt) * 2 * L * n;
+      build_power_table<L, T>(S, xpt, tab);
+      __syncthreads();
+      C<L> acc[CPL];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
+      process_chunks<L, SEG, CPL, T, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
+      write_row<L, CPL, T, MODE>(S, O, pt, p, acc, fpart);
+    }
+  }
+}
+
 }  // namespace pe

@@ -42,19 +42,12 @@ __device__ __forceinline__ C<L> c_mul_conj_a(const C<L>& a, const C<L>& b) {
 // overwritten; Rw gets R as [n][n+1] complex AoS (diagonal real); yw is
 // [n] complex AoS scratch for the back substitution; x is updated.
 template <int L, int T>
-__global__ __launch_bounds__(T) void mgs_solve_kernel(int N, int n, double* __restrict__ W, int64_t w_pt,
-                                                      double* __restrict__ Rw, int64_t r_pt,
-                                                      double* __restrict__ yw, int64_t y_pt,
-                                                      double* __restrict__ X, int64_t x_pt,
-                                                      double* __restrict__ resid) {
-  extern __shared__ double lds[];
-  const int pt = blockIdx.x;
+__device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __restrict__ Rm,
+                                double* __restrict__ Y, double* __restrict__ xp, double* __restrict__ res2,
+                                double* lds) {
   const int tid = threadIdx.x;
   const int ld = n + 1;
   const int64_t plane = int64_t(N) * ld;
-  double* A = W + pt * w_pt;
-  double* Rm = Rw + pt * r_pt;
-  double* Y = yw + pt * y_pt;
   double* colk = lds;                             // N complex, AoS
   double* sh = colk + size_t(N) * 2 * L;          // [0..L): |a_k|^2 of the next pivot
   double* red = sh + 2 * L;                       // T doubles for reductions
@@ -146,7 +139,6 @@ __global__ __launch_bounds__(T) void mgs_solve_kernel(int N, int n, double* __re
   }
   // update x and the step size
   double dmax = 0.0;
-  double* xp = X + pt * x_pt;
   for (int j = tid; j < n; j += T) {
     if (!singular) {
       const C<L> d = load_aos<L>(Y + size_t(j) * 2 * L);
@@ -160,10 +152,50 @@ __global__ __launch_bounds__(T) void mgs_solve_kernel(int N, int n, double* __re
     if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
     __syncthreads();
   }
-  if (tid == 0 && resid) {
-    resid[2 * pt] = fnorm;
-    resid[2 * pt + 1] = singular ? -1.0 : red[0];
+  if (tid == 0 && res2) {
+    res2[0] = fnorm;
+    res2[1] = singular ? -1.0 : red[0];
   }
+}
+
+// one system, P points: block pt solves point pt
+template <int L, int T>
+__global__ __launch_bounds__(T) void mgs_solve_kernel(int N, int n, double* __restrict__ W, int64_t w_pt,
+                                                      double* __restrict__ Rw, int64_t r_pt,
+                                                      double* __restrict__ yw, int64_t y_pt,
+                                                      double* __restrict__ X, int64_t x_pt,
+                                                      double* __restrict__ resid) {
+  extern __shared__ double lds[];
+  const int pt = blockIdx.x;
+  mgs_solve_point<L, T>(N, n, W + pt * w_pt, Rw + pt * r_pt, yw + pt * y_pt, X + pt * x_pt,
+                        resid ? resid + 2 * pt : nullptr, lds);
+}
+
+// Per-system description of a batched Newton step (offsets in doubles for
+// one point; a system's block for P points starts at P times its offset).
+struct BatchNewtonDesc {
+  int N, n;
+  int64_t w_off, r_off, y_off, x_off;
+};
+
+// batch: block b solves point (b % P) of system order[b / P]
+template <int L, int T>
+__global__ __launch_bounds__(T) void mgs_solve_batch_kernel(const BatchNewtonDesc* __restrict__ desc,
+                                                            const int* __restrict__ order, int P,
+                                                            double* __restrict__ W, double* __restrict__ Rw,
+                                                            double* __restrict__ yw, double* __restrict__ X,
+                                                            double* __restrict__ resid) {
+  extern __shared__ double lds[];
+  const int s = order[blockIdx.x / P];
+  const int pt = blockIdx.x - (blockIdx.x / P) * P;
+  const BatchNewtonDesc d = desc[s];
+  const int64_t w_pt = int64_t(2) * L * d.N * (d.n + 1);
+  const int64_t r_pt = int64_t(d.n) * (d.n + 1) * 2 * L;
+  const int64_t y_pt = int64_t(d.n) * 2 * L;
+  const int64_t x_pt = int64_t(2) * L * d.n;
+  mgs_solve_point<L, T>(d.N, d.n, W + d.w_off * P + pt * w_pt, Rw + d.r_off * P + pt * r_pt,
+                        yw + d.y_off * P + pt * y_pt, X + d.x_off * P + pt * x_pt,
+                        resid ? resid + (int64_t(s) * P + pt) * 2 : nullptr, lds);
 }
 
 template <int L>

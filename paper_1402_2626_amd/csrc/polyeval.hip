@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <mutex>
+#include <numeric>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -475,25 +476,278 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
 
 }  // extern "C"
 
-// ------------------------------------------------------------------ not yet available
+// ------------------------------------------------------------------ batches
+
+struct pe_batch {
+  int device = 0;
+  int level = 0;
+  int S = 0;
+  int seg = 4;
+  int cpl = 1;
+  size_t lds = 0;
+  int maxN = 0;
+  std::vector<const pe_system*> systems;
+  std::vector<int64_t> x_off, F_off, J_off;  // per point, doubles, [S+1]
+  std::vector<BatchNewtonDesc> ndesc;        // per point offsets of the Newton workspace
+  int64_t w_total = 0, r_total = 0, y_total = 0;  // per point, doubles
+  int64_t nitems = 0;
+  SysView* d_views = nullptr;
+  uint64_t* d_items = nullptr;
+  int64_t* d_offs = nullptr;  // x_off | F_off | J_off | W offsets, each [S+1]
+  BatchNewtonDesc* d_ndesc = nullptr;
+  int* d_order = nullptr;
+  int* d_counter = nullptr;
+  int grid = 0;
+};
+
+namespace {
+
+template <int L, int SEG, int CPL, int MODE>
+hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const BatchOut& out, hipStream_t st) {
+  auto kern = batch_rows_kernel<L, SEG, CPL, kThreads, MODE>;
+  if (b->lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds));
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kThreads, b->lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, b->nitems));
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kThreads), b->lds, st, (const SysView*)b->d_views,
+                     (const uint64_t*)b->d_items, b->nitems, b->d_counter, P, x, (const int64_t*)b->d_offs, out);
+  return hipGetLastError();
+}
+
+template <int L, int SEG>
+hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode,
+                              hipStream_t st) {
+  switch (b->cpl * 4 + mode) {
+#define PE_CASE(CPL, MODE) \
+  case CPL * 4 + MODE:     \
+    return launch_batch_t<L, SEG, CPL, MODE>(b, P, x, out, st);
+    PE_CASE(1, MODE_EVAL)
+    PE_CASE(1, MODE_FONLY)
+    PE_CASE(2, MODE_EVAL)
+    PE_CASE(2, MODE_FONLY)
+    PE_CASE(4, MODE_EVAL)
+    PE_CASE(4, MODE_FONLY)
+    PE_CASE(8, MODE_EVAL)
+    PE_CASE(8, MODE_FONLY)
+#undef PE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
+  if (b->level == 1 && b->seg == 8) return dispatch_batch_seg<1, 8>(b, P, x, out, mode, st);
+  if (b->level == 2 && b->seg == 4) return dispatch_batch_seg<2, 4>(b, P, x, out, mode, st);
+  if (b->level == 4 && b->seg == 4) return dispatch_batch_seg<4, 4>(b, P, x, out, mode, st);
+  return hipErrorInvalidValue;
+}
+
+void batch_free(pe_batch* b) {
+  for (void* p : {(void*)b->d_views, (void*)b->d_items, (void*)b->d_offs, (void*)b->d_ndesc, (void*)b->d_order,
+                  (void*)b->d_counter})
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+pe_status upload_raw(const std::vector<T>& v, T** dst, hipStream_t st) {
+  *dst = nullptr;
+  if (v.empty()) return PE_OK;
+  PE_HIP(hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)));
+  PE_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return PE_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-pe_status pe_batch_create(pe_batch** out, int32_t, const pe_system* const*, void*) {
-  if (out) *out = nullptr;
-  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream) {
+  if (!out) return fail(PE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (S < 1 || !systems) return fail(PE_EINVAL, "need at least one system");
+  auto* b = new (std::nothrow) pe_batch();
+  if (!b) return fail(PE_ENOMEM, "host allocation failed");
+  b->S = S;
+  b->systems.assign(systems, systems + S);
+  for (int s = 0; s < S; ++s)
+    if (!systems[s]) {
+      delete b;
+      return fail(PE_EINVAL, "system " + std::to_string(s) + " is NULL");
+    }
+  b->level = systems[0]->level;
+  b->seg = systems[0]->plan.seg;
+  b->device = systems[0]->device;
+  int maxcols = 1;
+  for (int s = 0; s < S; ++s) {
+    const pe_system* y = systems[s];
+    if (y->level != b->level || y->plan.seg != b->seg || y->device != b->device) {
+      delete b;
+      return fail(PE_EINVAL, "batched systems must share level, launch shape and device");
+    }
+    maxcols = std::max(maxcols, y->view.ncols);
+    b->lds = std::max(b->lds, y->plan.lds);
+    b->maxN = std::max(b->maxN, y->view.N);
+  }
+  b->cpl = cpl_bucket(maxcols, kThreads);
+  const int L = b->level;
+  // packed layout per point
+  b->x_off.assign(S + 1, 0);
+  b->F_off.assign(S + 1, 0);
+  b->J_off.assign(S + 1, 0);
+  std::vector<int64_t> w_off(S + 1, 0);
+  b->ndesc.resize(S);
+  int64_t ro = 0, yo = 0;
+  for (int s = 0; s < S; ++s) {
+    const int n = systems[s]->view.n, N = systems[s]->view.N;
+    b->x_off[s + 1] = b->x_off[s] + int64_t(2) * L * n;
+    b->F_off[s + 1] = b->F_off[s] + int64_t(2) * L * N;
+    b->J_off[s + 1] = b->J_off[s] + int64_t(2) * L * N * n;
+    w_off[s + 1] = w_off[s] + int64_t(2) * L * N * (n + 1);
+    BatchNewtonDesc& d = b->ndesc[s];
+    d.N = N;
+    d.n = n;
+    d.w_off = w_off[s];
+    d.r_off = ro;
+    d.y_off = yo;
+    d.x_off = b->x_off[s];
+    ro += int64_t(n) * (n + 1) * 2 * L;
+    yo += int64_t(n) * 2 * L;
+  }
+  b->w_total = w_off[S];
+  b->r_total = ro;
+  b->y_total = yo;
+  // work items in decreasing cost (longest processing time first)
+  std::vector<std::pair<int64_t, uint64_t>> items;
+  for (int s = 0; s < S; ++s) {
+    const Packed& H = systems[s]->host;
+    for (int p = 0; p < H.N; ++p) items.push_back({H.poly_cost[p], (uint64_t(s) << 32) | uint64_t(p)});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+  std::vector<uint64_t> it(items.size());
+  for (size_t i = 0; i < items.size(); ++i) it[i] = items[i].second;
+  b->nitems = int64_t(it.size());
+  std::vector<SysView> views(S);
+  for (int s = 0; s < S; ++s) views[s] = systems[s]->view;
+  std::vector<int64_t> offs;
+  offs.insert(offs.end(), b->x_off.begin(), b->x_off.end());
+  offs.insert(offs.end(), b->F_off.begin(), b->F_off.end());
+  offs.insert(offs.end(), b->J_off.begin(), b->J_off.end());
+  offs.insert(offs.end(), w_off.begin(), w_off.end());
+  std::vector<int> order(S);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return int64_t(systems[a]->view.n) * systems[a]->view.N > int64_t(systems[c]->view.n) * systems[c]->view.N;
+  });
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  pe_status e = PE_OK;
+  if ((e = upload_raw(views, &b->d_views, hs)) != PE_OK || (e = upload_raw(it, &b->d_items, hs)) != PE_OK ||
+      (e = upload_raw(offs, &b->d_offs, hs)) != PE_OK || (e = upload_raw(b->ndesc, &b->d_ndesc, hs)) != PE_OK ||
+      (e = upload_raw(order, &b->d_order, hs)) != PE_OK) {
+    batch_free(b);
+    delete b;
+    return e;
+  }
+  hipError_t he = hipMalloc(reinterpret_cast<void**>(&b->d_counter), sizeof(int));
+  if (he == hipSuccess) he = hipStreamSynchronize(hs);
+  if (he != hipSuccess) {
+    batch_free(b);
+    delete b;
+    return fail(PE_EDEVICE, std::string("batch upload: ") + hipGetErrorString(he));
+  }
+  *out = b;
+  return PE_OK;
 }
-pe_status pe_batch_destroy(pe_batch*) { return PE_OK; }
-pe_status pe_batch_layout(const pe_batch*, int64_t*, int64_t*, int64_t*) {
-  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+
+pe_status pe_batch_destroy(pe_batch* b) {
+  if (!b) return PE_OK;
+  batch_free(b);
+  delete b;
+  return PE_OK;
 }
-pe_status pe_batch_eval(const pe_batch*, int32_t, const double*, double*, double*, void*) {
-  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+
+pe_status pe_batch_layout(const pe_batch* b, int64_t* x_off, int64_t* F_off, int64_t* J_off) {
+  if (!b) return fail(PE_EINVAL, "batch is NULL");
+  for (int s = 0; s <= b->S; ++s) {
+    if (x_off) x_off[s] = b->x_off[s];
+    if (F_off) F_off[s] = b->F_off[s];
+    if (J_off) J_off[s] = b->J_off[s];
+  }
+  return PE_OK;
 }
-size_t pe_batch_newton_workspace_bytes(const pe_batch*, int32_t) { return 0; }
-pe_status pe_batch_newton_step(const pe_batch*, int32_t, double*, void*, double*, void*) {
-  return fail(PE_EUNSUPPORTED, "batches are not available in this build");
+
+pe_status pe_batch_eval(const pe_batch* b, int32_t P, const double* x, double* F, double* J, void* stream) {
+  if (!b) return fail(PE_EINVAL, "batch is NULL");
+  if (P < 0) return fail(PE_EINVAL, "points_per_system must be nonnegative");
+  if (P == 0 || b->nitems == 0) return PE_OK;
+  if (!x || !F) return fail(PE_EINVAL, "x or F is NULL");
+  BatchOut out;
+  out.J = J;
+  out.J_off = b->d_offs + 2 * (b->S + 1);
+  out.F = F;
+  out.F_off = b->d_offs + (b->S + 1);
+  out.newton = 0;
+  hipError_t e = dispatch_batch(b, P, x, out, J ? MODE_EVAL : MODE_FONLY, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+  return PE_OK;
 }
+
+size_t pe_batch_newton_workspace_bytes(const pe_batch* b, int32_t P) {
+  if (!b || P < 0) return 0;
+  // [W blocks][R blocks][y blocks]
+  return align256(size_t(P) * b->w_total * 8) + align256(size_t(P) * b->r_total * 8) +
+         align256(size_t(P) * b->y_total * 8);
+}
+
+pe_status pe_batch_newton_step(const pe_batch* b, int32_t P, double* x_inout, void* workspace, double* resid_out,
+                               void* stream) {
+  if (!b) return fail(PE_EINVAL, "batch is NULL");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  if (P == 0) return PE_OK;
+  if (!x_inout || !workspace) return fail(PE_EINVAL, "x or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
+  for (const pe_system* y : b->systems) {
+    pe_status ps = newton_check(y, P);
+    if (ps != PE_OK) return ps;
+  }
+  const int L = b->level;
+  char* base = static_cast<char*>(workspace);
+  double* W = reinterpret_cast<double*>(base);
+  double* Rw = reinterpret_cast<double*>(base + align256(size_t(P) * b->w_total * 8));
+  double* Yw = reinterpret_cast<double*>(base + align256(size_t(P) * b->w_total * 8) + align256(size_t(P) * b->r_total * 8));
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  BatchOut out;
+  out.J = W;
+  out.J_off = b->d_offs + 3 * (b->S + 1);
+  out.F = nullptr;
+  out.F_off = nullptr;
+  out.newton = 1;
+  hipError_t e = dispatch_batch(b, P, x_inout, out, MODE_EVAL, hs);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("batch newton eval: ") + hipGetErrorString(e));
+  size_t lds = L == 1 ? mgs_lds_bytes<1>(b->maxN) : (L == 2 ? mgs_lds_bytes<2>(b->maxN) : mgs_lds_bytes<4>(b->maxN));
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 65536) {
+      hipError_t e2 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e2 != hipSuccess) return e2;
+    }
+    hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(b->S) * P)), dim3(kMgsThreads), lds, hs,
+                       (const BatchNewtonDesc*)b->d_ndesc, (const int*)b->d_order, P, W, Rw, Yw, x_inout, resid_out);
+    return hipGetLastError();
+  };
+  if (L == 1) e = go(mgs_solve_batch_kernel<1, kMgsThreads>);
+  if (L == 2) e = go(mgs_solve_batch_kernel<2, kMgsThreads>);
+  if (L == 4) e = go(mgs_solve_batch_kernel<4, kMgsThreads>);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("batch newton solve: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
 pe_status pe_autotune(pe_system*, int32_t, void*) { return PE_OK; }
 pe_status pe_set_plan_cache(const char*) { return PE_OK; }
 
