@@ -25,8 +25,8 @@ converted exactly by summing their limbs.
 Also here: the absolute sums that normalise the error metric, rounding of
 exact values to level-L limbs, the adjoint J^H v by its definition, and a
 Gauss-Newton step (Section 4, Problem Statement) whose least-squares solve is
-mpmath's Householder QR at high precision (not modified Gram-Schmidt, so it
-shares no algorithm with the library's solver).
+mpmath's Householder QR factorisation at high precision (not modified
+Gram-Schmidt, so it shares no algorithm with the library's solver).
 """
 from __future__ import annotations
 
@@ -384,8 +384,9 @@ def adjoint_columns(sys_, x: np.ndarray, v: np.ndarray, cols: Iterable[int]):
 def gauss_newton_step_mp(sys_, X_exact, prec: int = 512):
     """One Gauss-Newton step from the exact point ``X_exact``.
 
-    A = J(x), b = -F(x) exactly; the least-squares correction is mpmath's
-    Householder QR solve at ``prec`` bits; returns the new point as exact
+    A = J(x), b = -F(x) exactly; the least-squares correction comes from
+    mpmath's Householder QR (``mpmath.qr``) at ``prec`` bits, dx = R^-1 Q^H b;
+    returns the new point as exact
     dyadic values (each mpmath component converted exactly) and
     ``(|F(x)|_2, |dx|_inf)`` as floats."""
     import mpmath
@@ -413,13 +414,12 @@ def gauss_newton_step_mp(sys_, X_exact, prec: int = 512):
             for j, val in J[p].items():
                 A[p, j] = mpc(val)
             b[p] = -mpc(F[p])
-        dx, _res = mpmath.qr_solve(A, b)
+        # least squares: A = QR (Householder, mpmath.qr), then R dx = Q^H b
+        Q, Rm = mpmath.qr(A, mode="skinny")
+        dx = mpmath.lu_solve(Rm, Q.H * b)
         fnorm = float(mpmath.norm(b, 2))
         dinf = float(max(abs(dx[j]) for j in range(n))) if n else 0.0
-        newX = []
-        for j in range(n):
-            z = mpc(X_exact[j]) + dx[j]
-            newX.append(_mpc_to_cdy(z))
+        newX = [_mpc_to_cdy(mpc(X_exact[j]) + dx[j]) for j in range(n)]
     return newX, (fnorm, dinf)
 
 

@@ -351,19 +351,24 @@ def pin_abs_sums() -> bool:
 # ---------------------------------------------------------------- Gauss-Newton
 
 def pin_gauss_newton_linear() -> bool:
-    """For F = C x - b (overdetermined), one Gauss-Newton step from any point
-    lands on the least-squares solution; against numpy.linalg.lstsq."""
+    """For F = C x - b (overdetermined, inconsistent, with zeros on the
+    diagonal of C), one Gauss-Newton step from any point lands on the
+    least-squares solution; against numpy.linalg.lstsq."""
     rng = synth.rng_for(71)
-    N, n = 6, 3
-    C = rng.integers(-4, 5, size=(N, n)) + 1j * rng.integers(-4, 5, size=(N, n))
-    b = rng.integers(-4, 5, size=N) + 1j * rng.integers(-4, 5, size=N)
-    polys = [[(C[p, j], [(j, 1)]) for j in range(n) if C[p, j] != 0] + [(-b[p], [])] for p in range(N)]
-    sys_ = synth.from_monomial_lists(2, n, polys)
-    X0 = [(1, 0, 0)] * n
-    X1, _ = O.gauss_newton_step_mp(sys_, X0, prec=256)
-    want = np.linalg.lstsq(C, b, rcond=None)[0]
-    got = np.array([O.cdy_to_complex(v) for v in X1])
-    return bool(np.max(np.abs(got - want)) < 1e-12)
+    for N, n in ((6, 3), (9, 9), (12, 5)):
+        C = rng.integers(-4, 5, size=(N, n)) + 1j * rng.integers(-4, 5, size=(N, n))
+        for i in range(min(N, n)):
+            C[i, i] = 0
+        b = rng.integers(-4, 5, size=N) + 1j * rng.integers(-4, 5, size=N)
+        polys = [[(C[p, j], [(j, 1)]) for j in range(n) if C[p, j] != 0] + [(-b[p], [])] for p in range(N)]
+        sys_ = synth.from_monomial_lists(2, n, polys)
+        X0 = [(1, 0, 0)] * n
+        X1, _ = O.gauss_newton_step_mp(sys_, X0, prec=256)
+        want = np.linalg.lstsq(C, b, rcond=None)[0]
+        got = np.array([O.cdy_to_complex(v) for v in X1])
+        if not np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want))):
+            return False
+    return True
 
 
 def pin_gauss_newton_quadratic() -> bool:

@@ -81,7 +81,8 @@ def test_newton_dd_n256_planted(pe):
         errs.append(_dist(xd.cpu().numpy()[0], Xs, 2))
         res.append(r.cpu().numpy()[0].copy())
     U.flush(f"newton dd_n256: errors {errs}, residuals {res}")
-    assert errs[0] <= 1e-9 and errs[1] <= 1e-20 and errs[-1] <= 1e-26, errs
+    # quadratic decay (e1 <= C e0^2) down to the double-double floor
+    assert errs[0] <= 1e-8 and errs[1] <= 1e4 * errs[0] ** 2 and errs[-1] <= 1e-29, errs
     assert res[0][0] > res[1][0] > res[2][0]
     S.close()
 
