@@ -25,6 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "dd_n256"
+LEVEL_NAME = {1: "double", 2: "double-double", 4: "quad-double"}
+
+
+def describe(name):
+    from paper_1402_2626_amd import synth
+    if name == "dd_batch4096":
+        return ("dd_batch4096: 4096 systems, n = N = m uniform in {32,64,128,256}, k = min(16, n/4), "
+                "exps {1..3}, 8 points each, one persistent launch")
+    w = synth.WORKLOADS[name]
+    return (f"{name}: n={w['n']}, N={w['N']}, {w['m']} monomials/poly, k={w['k']}, "
+            f"exps {{1..{w['exp_hi']}}}, {w['P']} point(s)")
 PEAK_FP64_TFLOPS = 78.6  # 256 CUs x 64 FP64 FMA lanes/clk x 2 flops x 2.4 GHz
 
 
@@ -60,6 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512 "
+                         "and dd_batch4096 print the same kind of line for context")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -69,7 +83,11 @@ def main():
     from paper_1402_2626_amd import synth
     from paper_1402_2626_amd import workmodel as W
 
-    sys_, x = synth.workload(WORKLOAD)
+    if args.workload == "dd_batch4096":
+        return bench_batch(args)
+    if args.workload == "dd_adjoint_1024x512":
+        return bench_adjoint(args)
+    sys_, x = synth.workload(args.workload)
     P = x.shape[0]
 
     cpu = None
@@ -113,7 +131,7 @@ def main():
     flops = W.flops_per_point(sys_) * P
     achieved = flops / (kern_ms * 1e-3) / 1e12
     out = {
-        "metric": "monomial eval+grad/s (complex DD, F + full J)",
+        "metric": "monomial eval+grad/s (complex %s, F + full J)" % LEVEL_NAME[sys_.level],
         "value": M * P * K / dt,
         "unit": "monomials/s",
         "n_gpus": 1,
@@ -123,9 +141,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 (double-double complex)",
+        "dtype": "f64 (%s complex)" % LEVEL_NAME[sys_.level],
         "data": "synthetic",
-        "config": {"workload": "dd_n256: n=256, N=256, 256 monomials/poly, k=16, exps {1..4}, 1 point",
+        "config": {"workload": describe(args.workload),
                    "points": P, "monomials": M, "occurrences": sys_.nnz,
                    "F_plus_J_per_s": P * K / dt, "kernel_ms": kern_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -133,6 +151,111 @@ def main():
         "cpu_baseline": cpu,
     }
     S.close()
+    print(json.dumps(out), flush=True)
+
+
+def _time_steps(fn, K, W, stream):
+    import torch
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return dt, sum(a.elapsed_time(b) for a, b in ev) / K
+
+
+def bench_adjoint(args):
+    """g = J^H v for the overdetermined DD system (N = 1024, n = 512, k = 24)
+    at 64 points; J is never formed."""
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    sys_, x = synth.workload("dd_adjoint_1024x512")
+    v = synth.adjoint_vectors(0, x.shape[0], sys_.n_polys, sys_.level)
+    P = x.shape[0]
+    S = pe.System.from_sparse(sys_)
+    xd, vd = torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda()
+    g = torch.empty_like(xd)
+    st = torch.cuda.current_stream()
+    dt, ms = _time_steps(lambda: S.adjoint(xd, vd, out=g, stream=st), args.steps, args.warmup, st)
+    flops = W.flops_per_point(sys_) * P
+    out = {"metric": "monomial adjoint (J^H v) evals/s (complex double-double)",
+           "value": sys_.n_monomials * P * args.steps / dt, "unit": "monomials/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 (double-double complex)",
+           "data": "synthetic", "config": {"workload": describe("dd_adjoint_1024x512"), "points": P,
+                                           "step_ms_events": ms},
+           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """4096 uneven DD systems at 8 points each in one persistent launch,
+    beside the plain path (one pe_eval launch per system)."""
+    import numpy as np
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    S_count, P = 4096, 8
+    ns = synth.batch_sizes(0, S_count)
+    t0 = time.perf_counter()
+    systems, dev, flops, mons = [], [], 0.0, 0
+    for i in range(S_count):
+        sy = synth.batch_system(0, i, int(ns[i]))
+        dev.append(pe.System.from_sparse(sy))
+        flops += W.flops_per_point(sy) * P
+        mons += sy.n_monomials * P
+        del sy
+        if i % 512 == 0:
+            print(f"# loaded {i} systems, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    B = pe.Batch(dev)
+    rng = synth.rng_for((0, 9))
+    x = torch.from_numpy(np.concatenate([synth.unit_circle_points(rng, P, int(n), 2).reshape(-1)
+                                         for n in ns])).cuda()
+    F = torch.empty(int(B.F_off[-1]) * P, dtype=torch.float64, device="cuda")
+    J = torch.empty(int(B.J_off[-1]) * P, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K = max(1, min(args.steps, 5))
+    dt, ms = _time_steps(lambda: B.eval(x, P, out=(F, J), stream=st), K, 1, st)
+    # plain path: one launch per system
+    offs = [(int(B.x_off[i]) * P, int(B.F_off[i]) * P, int(B.J_off[i]) * P) for i in range(S_count)]
+    views = []
+    for i in range(S_count):
+        n = int(ns[i])
+        xo, fo, jo = offs[i]
+        views.append((x[xo:xo + P * 4 * n].view(P, 2, 2, n), F[fo:fo + P * 4 * n].view(P, 2, 2, n),
+                      J[jo:jo + P * 4 * n * n].view(P, 2, 2, n, n)))
+
+    def plain():
+        for i in range(S_count):
+            xv, fv, jv = views[i]
+            dev[i].eval(xv, out=(fv, jv), stream=st)
+    dt_plain, ms_plain = _time_steps(plain, 1, 1, st)
+    out = {"metric": "monomial eval+grad/s (complex double-double, batched uneven systems)",
+           "value": mons * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K, "warmup": 1,
+           "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 (double-double complex)", "data": "synthetic",
+           "config": {"workload": describe("dd_batch4096"), "system_points_per_s": S_count * P * K / dt,
+                      "plain_path_ms": dt_plain * 1e3, "plain_monomials_per_s": mons / dt_plain,
+                      "monomials": mons},
+           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

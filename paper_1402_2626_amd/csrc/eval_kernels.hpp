@@ -149,20 +149,27 @@ __device__ void build_power_table(const SysView& S, const double* __restrict__ x
 }
 
 // ------------------------------------------------------------------ one chunk
+//
+// A chunk is processed by a SUB-GROUP of kSub = 256 threads (lt = local
+// thread index).  A workgroup of G sub-groups works on G consecutive chunks of
+// its row at once, each sub-group with its own LDS slot region and its own
+// register accumulators; the G partial rows are added in sub-group order at
+// the end, so the result does not depend on timing.
+
+constexpr int kSub = 256;
 
 // Monomial phase of one chunk: writes every contribution of the chunk into
-// its LDS slot.  All lanes of the workgroup call it (the butterfly needs the
+// its LDS slot.  All lanes of the sub-group call it (the butterfly needs the
 // whole wavefront).  In MODE_ADJ the coefficient of a monomial of polynomial
 // p is multiplied by conj(v_p).
 template <int L, int SEG, int MODE>
-__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDesc& cd,
+__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDesc& cd, int lt,
                                                 const double* __restrict__ xpt,
                                                 const double* __restrict__ vpt, const double* tab,
                                                 double* contrib) {
-  const int tid = threadIdx.x;
   const int s = cd.s;
-  const int g = tid / s;
-  const int q = tid & (s - 1);
+  const int g = lt / s;
+  const int q = lt & (s - 1);
   const bool active = g < int(cd.count);
 
   int k = 0, fslot = 0;
@@ -187,7 +194,7 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
 #pragma unroll
   for (int i = 0; i < SEG; ++i) {
     if (i < len) {
-      const OccRec r = S.occ[cd.occ_base + size_t(i) * cd.width + tid];
+      const OccRec r = S.occ[cd.occ_base + size_t(i) * cd.width + lt];
       const int v = r.var, d = r.exp;
       xv[i] = load_planar<L>(xpt, S.n, v);
       if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
@@ -236,21 +243,23 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
 }
 
 // Owner phase: add the chunk's slots into the register accumulators.
-template <int L, int CPL, int T, int MODE>
-__device__ __forceinline__ void chunk_owners(const SysView& S, const int (&cb)[CPL], const int (&ce)[CPL],
-                                             const double* contrib, C<L> (&acc)[CPL]) {
+template <int L, int CPL>
+__device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&ce)[CPL], const double* contrib,
+                                             C<L> (&acc)[CPL]) {
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     for (int sl = cb[cc]; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], load_aos<L>(contrib + size_t(sl) * (2 * L)));
   }
 }
 
-template <int CPL, int T, int MODE>
-__device__ __forceinline__ void chunk_colptr(const SysView& S, const ChunkDesc& cd, int (&cb)[CPL], int (&ce)[CPL]) {
+// Columns of the accumulator slot cc of local thread lt: lt + cc * kSub.
+template <int CPL, int MODE>
+__device__ __forceinline__ void chunk_colptr(const SysView& S, const ChunkDesc& cd, bool act, int lt,
+                                             int (&cb)[CPL], int (&ce)[CPL]) {
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    const int c = threadIdx.x + cc * T;
-    bool use = c < S.ncols;
+    const int c = lt + cc * kSub;
+    bool use = act && c < S.ncols;
     if (MODE == MODE_FONLY) use = use && c >= S.n;
     if (MODE == MODE_ADJ) use = use && c < S.n;
     if (use) {
@@ -263,32 +272,70 @@ __device__ __forceinline__ void chunk_colptr(const SysView& S, const ChunkDesc& 
   }
 }
 
-// Process chunks [ch0, ch1) into the accumulators.
-template <int L, int SEG, int CPL, int T, int MODE>
-__device__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1, const double* __restrict__ xpt,
-                               const double* __restrict__ vpt, const double* tab, double* contrib,
+// Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
+// ch0 + sg, ch0 + sg + G, ...
+template <int L, int SEG, int CPL, int G, int MODE>
+__device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1, const double* __restrict__ xpt,
+                               const double* __restrict__ vpt, const double* tab, double* contrib_base,
                                C<L> (&acc)[CPL]) {
-  for (uint32_t ch = ch0; ch < ch1; ++ch) {
-    const ChunkDesc cd = S.chunks[ch];
+  const int sg = threadIdx.x / kSub;
+  const int lt = threadIdx.x - sg * kSub;
+  double* contrib = contrib_base + size_t(sg) * S.max_slots * 2 * L;
+  for (uint32_t base = ch0; base < ch1; base += G) {
+    const uint32_t ch = base + sg;
+    const bool act = ch < ch1;
+    ChunkDesc cd;
+    if (act) {
+      cd = S.chunks[ch];
+    } else {
+      cd = ChunkDesc{};
+      cd.s = 1;
+    }
     int cb[CPL], ce[CPL];
-    chunk_colptr<CPL, T, MODE>(S, cd, cb, ce);
-    chunk_monomials<L, SEG, MODE>(S, cd, xpt, vpt, tab, contrib);
+    chunk_colptr<CPL, MODE>(S, cd, act, lt, cb, ce);
+    chunk_monomials<L, SEG, MODE>(S, cd, lt, xpt, vpt, tab, contrib);
     __syncthreads();
-    chunk_owners<L, CPL, T, MODE>(S, cb, ce, contrib, acc);
+    chunk_owners<L, CPL>(cb, ce, contrib, acc);
     __syncthreads();
   }
 }
 
-// Write row p of J and F from the accumulators (EVAL / FONLY).
-template <int L, int CPL, int T, int MODE>
-__device__ void write_row(const SysView& S, const OutView& O, int pt, int p, const C<L> (&acc)[CPL], double* fpart) {
+// Write row p of J and F from the accumulators (EVAL / FONLY).  With G > 1
+// sub-groups 1..G-1 first hand their partial rows to sub-group 0 through
+// LDS (the contribution region is free by then), which adds them in order.
+template <int L, int CPL, int G, int MODE>
+__device__ __forceinline__ void write_row(const SysView& S, const OutView& O, int pt, int p, C<L> (&acc)[CPL], double* scratch,
+                          double* fpart) {
+  const int sg = threadIdx.x / kSub;
+  const int lt = threadIdx.x - sg * kSub;
+  if (G > 1) {
+    if (sg > 0) {
 #pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) {
-    const int c = threadIdx.x + cc * T;
-    if (c < S.n) {
-      if (MODE == MODE_EVAL) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
-    } else if (c < S.ncols) {
-      store_aos(fpart + size_t(c - S.n) * (2 * L), acc[cc]);
+      for (int cc = 0; cc < CPL; ++cc) {
+        const int c = lt + cc * kSub;
+        if (c < S.ncols) store_aos(scratch + (size_t(sg - 1) * S.ncols + c) * (2 * L), acc[cc]);
+      }
+    }
+    __syncthreads();
+    if (sg == 0) {
+      for (int o = 1; o < G; ++o) {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          const int c = lt + cc * kSub;
+          if (c < S.ncols) acc[cc] = c_add(acc[cc], load_aos<L>(scratch + (size_t(o - 1) * S.ncols + c) * (2 * L)));
+        }
+      }
+    }
+  }
+  if (sg == 0) {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int c = lt + cc * kSub;
+      if (c < S.n) {
+        if (MODE == MODE_EVAL) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
+      } else if (c < S.ncols) {
+        store_aos(fpart + size_t(c - S.n) * (2 * L), acc[cc]);
+      }
     }
   }
   __syncthreads();
@@ -301,74 +348,79 @@ __device__ void write_row(const SysView& S, const OutView& O, int pt, int p, con
   __syncthreads();
 }
 
-// LDS layout of a workgroup: [power table][contribution slots][F partials]
+// LDS layout of a workgroup: [power table][G contribution regions][F partials]
 template <int L>
-__host__ __device__ inline size_t lds_bytes(int n, int tab_last, int max_slots, int R) {
+__host__ __device__ inline size_t lds_bytes(int n, int tab_last, int max_slots, int R, int G) {
   const size_t tab = tab_last >= 2 ? size_t(tab_last - 1) * n : 0;
-  return (tab + size_t(max_slots) + size_t(R)) * 2 * L * sizeof(double);
+  return (tab + size_t(G) * max_slots + size_t(R)) * 2 * L * sizeof(double);
+}
+
+__device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
+  return S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0;
 }
 
 // ------------------------------------------------------------------ kernels
 
-// grid: P * N workgroups, block (pt, p) = (blockIdx.x / N, blockIdx.x % N)
-template <int L, int SEG, int CPL, int T, int MODE>
-__global__ __launch_bounds__(T) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
-                                                      int64_t x_pt) {
+// grid: P * N workgroups of G * 256 threads, block (pt, p) = (blockIdx.x / N,
+// blockIdx.x % N)
+template <int L, int SEG, int CPL, int G, int MODE>
+__global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
+                                                             int64_t x_pt) {
   extern __shared__ double lds[];
   const int pt = blockIdx.x / S.N;
   const int p = blockIdx.x - pt * S.N;
   const double* xpt = x + pt * x_pt;
   double* tab = lds;
-  double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0);
-  double* fpart = contrib + size_t(S.max_slots) * 2 * L;
-  build_power_table<L, T>(S, xpt, tab);
+  double* contrib = lds + tab_doubles(S, L);
+  double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
+  build_power_table<L, G * kSub>(S, xpt, tab);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, T, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
-  write_row<L, CPL, T, MODE>(S, O, pt, p, acc, fpart);
+  process_chunks<L, SEG, CPL, G, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
+  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
 }
 
-// Adjoint: grid P * G workgroups; group gi covers polynomials
-// [gi * gsize, min(N, (gi+1) * gsize)).  Writes partial rows
-// part[(pt * G + gi)][2][L][n] (planar, plane stride n).
-template <int L, int SEG, int CPL, int T>
-__global__ __launch_bounds__(T) void adjoint_rows_kernel(SysView S, const double* __restrict__ x, int64_t x_pt,
-                                                         const double* __restrict__ v, int64_t v_pt, int G,
-                                                         int gsize, double* __restrict__ part) {
+// Adjoint: grid P * NG workgroups of 256 threads; group gi covers
+// polynomials [gi * gsize, min(N, (gi+1) * gsize)).  Writes partial rows
+// part[(pt * NG + gi)][2][L][n] (planar, plane stride n).
+template <int L, int SEG, int CPL>
+__global__ __launch_bounds__(kSub) void adjoint_rows_kernel(SysView S, const double* __restrict__ x, int64_t x_pt,
+                                                            const double* __restrict__ v, int64_t v_pt, int NG,
+                                                            int gsize, double* __restrict__ part) {
   extern __shared__ double lds[];
-  const int pt = blockIdx.x / G;
-  const int gi = blockIdx.x - pt * G;
+  const int pt = blockIdx.x / NG;
+  const int gi = blockIdx.x - pt * NG;
   const double* xpt = x + pt * x_pt;
   const double* vpt = v + pt * v_pt;
   double* tab = lds;
-  double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0);
-  build_power_table<L, T>(S, xpt, tab);
+  double* contrib = lds + tab_doubles(S, L);
+  build_power_table<L, kSub>(S, xpt, tab);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
   const int p0 = gi * gsize;
   const int p1 = min(S.N, p0 + gsize);
-  process_chunks<L, SEG, CPL, T, MODE_ADJ>(S, S.chunk_ptr[p0], S.chunk_ptr[p1], xpt, vpt, tab, contrib, acc);
-  double* out = part + size_t(pt * G + gi) * 2 * L * S.n;
+  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, S.chunk_ptr[p0], S.chunk_ptr[p1], xpt, vpt, tab, contrib, acc);
+  double* out = part + size_t(pt * NG + gi) * 2 * L * S.n;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    const int c = threadIdx.x + cc * T;
+    const int c = threadIdx.x + cc * kSub;
     if (c < S.n) store_planar(out, S.n, c, acc[cc]);
   }
 }
 
 // g[pt][.][.][j] = conj(sum over groups of part[pt][gi][.][.][j]) in group order
 template <int L>
-__global__ void adjoint_reduce_kernel(int n, int G, int P, const double* __restrict__ part, double* __restrict__ g) {
+__global__ void adjoint_reduce_kernel(int n, int NG, int P, const double* __restrict__ part, double* __restrict__ g) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(P) * n) return;
   const int pt = int(idx / n);
   const int j = int(idx - int64_t(pt) * n);
   C<L> s = c_zero<L>();
-  for (int gi = 0; gi < G; ++gi) s = c_add(s, load_planar<L>(part + size_t(pt * G + gi) * 2 * L * n, n, j));
+  for (int gi = 0; gi < NG; ++gi) s = c_add(s, load_planar<L>(part + size_t(pt * NG + gi) * 2 * L * n, n, j));
   store_planar(g + size_t(pt) * 2 * L * n, n, j, c_conj(s));
 }
 
@@ -393,11 +445,11 @@ __global__ void reset_counter_kernel(int* counter) {
 // device counter in the order of `items` (decreasing cost) until none is
 // left; each item is evaluated at all P points.  Every workgroup reaches the
 // exit test after every item, so the grid drains.
-template <int L, int SEG, int CPL, int T, int MODE>
-__global__ __launch_bounds__(T) void batch_rows_kernel(const SysView* __restrict__ views,
-                                                       const uint64_t* __restrict__ items, int64_t nitems,
-                                                       int* counter, int P, const double* __restrict__ x,
-                                                       const int64_t* __restrict__ x_off, BatchOut out) {
+template <int L, int SEG, int CPL, int MODE>
+__global__ __launch_bounds__(kSub) void batch_rows_kernel(const SysView* __restrict__ views,
+                                                          const uint64_t* __restrict__ items, int64_t nitems,
+                                                          int* counter, int P, const double* __restrict__ x,
+                                                          const int64_t* __restrict__ x_off, BatchOut out) {
   extern __shared__ double lds[];
   __shared__ int64_t item_sh;
   for (;;) {
@@ -435,17 +487,17 @@ __global__ __launch_bounds__(T) void batch_rows_kernel(const SysView* __restrict
       O.f_sign = 1.0;
     }
     double* tab = lds;
-    double* contrib = lds + (S.tab_last >= 2 ? size_t(S.tab_last - 1) * n * 2 * L : 0);
+    double* contrib = lds + tab_doubles(S, L);
     double* fpart = contrib + size_t(S.max_slots) * 2 * L;
     for (int pt = 0; pt < P; ++pt) {
       const double* xpt = x + x_off[s] * P + int64_t(pt) * 2 * L * n;
-      build_power_table<L, T>(S, xpt, tab);
+      build_power_table<L, kSub>(S, xpt, tab);
       __syncthreads();
       C<L> acc[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-      process_chunks<L, SEG, CPL, T, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
-      write_row<L, CPL, T, MODE>(S, O, pt, p, acc, fpart);
+      process_chunks<L, SEG, CPL, 1, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
+      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib, fpart);
     }
   }
 }

@@ -39,11 +39,11 @@ pe_status fail(pe_status st, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                              \
   } while (0)
 
-constexpr int kThreads = 256;
-
+// chunk slot budget per level: about 36 KB of LDS for D and DD (so that a
+// workgroup can hold four chunks at once), 68 KB for QD
 int default_seg(int L) { return L == 1 ? 8 : 4; }
 
-int default_slots(int L) { return L == 1 ? 4096 : (L == 2 ? 2048 : 1088); }
+int default_slots(int L) { return L == 1 ? 2304 : (L == 2 ? 1152 : 1088); }
 
 int cpl_bucket(int ncols, int T) {
   int c = (ncols + T - 1) / T;
@@ -70,12 +70,13 @@ struct DevBuf {
 }  // namespace
 
 struct Plan {
-  int T = kThreads;
+  int G = 1;  // chunks processed at once (workgroup of G * 256 threads)
   int seg = 4;
   int cpl = 1;
   int max_slots = 2048;
   int tab_last = 0;
-  size_t lds = 0;
+  size_t lds = 0;   // this plan's workgroup LDS
+  size_t lds1 = 0;  // LDS of a one-chunk workgroup (adjoint and batches)
 };
 
 struct pe_system {
@@ -96,88 +97,107 @@ struct pe_system {
 
 namespace {
 
-template <int L, int SEG, int CPL, int MODE>
+template <int L, int SEG, int CPL, int G, int MODE>
 hipError_t launch_rows_t(const pe_system* sys, int P, const double* x, const OutView& O, hipStream_t st) {
-  auto kern = eval_rows_kernel<L, SEG, CPL, kThreads, MODE>;
+  auto kern = eval_rows_kernel<L, SEG, CPL, G, MODE>;
   const size_t lds = sys->plan.lds;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
   const int64_t blocks = int64_t(P) * sys->view.N;
-  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(kThreads), lds, st, sys->view, O, x,
+  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), lds, st, sys->view, O, x,
                      int64_t(2) * L * sys->view.n);
   return hipGetLastError();
 }
 
 template <int L, int SEG, int CPL>
-hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
-  auto kern = adjoint_rows_kernel<L, SEG, CPL, kThreads>;
-  const size_t lds = sys->plan.lds;
+  auto kern = adjoint_rows_kernel<L, SEG, CPL>;
+  const size_t lds = sys->plan.lds1;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
   const int n = sys->view.n;
-  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * G)), dim3(kThreads), lds, st, sys->view, x,
-                     int64_t(2) * L * n, v, int64_t(2) * L * sys->view.N, G, gsize, part);
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(kSub), lds, st, sys->view, x,
+                     int64_t(2) * L * n, v, int64_t(2) * L * sys->view.N, NG, gsize, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = int64_t(P) * n;
-  hipLaunchKernelGGL(adjoint_reduce_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, n, G, P,
+  hipLaunchKernelGGL(adjoint_reduce_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, n, NG, P,
                      (const double*)part, g);
   return hipGetLastError();
 }
 
-// dispatch over (SEG, CPL, MODE) for a level
+// dispatch over (G, CPL, MODE) for a level
 template <int L, int SEG>
 hipError_t dispatch_rows_seg(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                              hipStream_t st) {
-  switch (sys->plan.cpl * 4 + mode) {
-#define PE_CASE(CPL, MODE) \
-  case CPL * 4 + MODE:     \
-    return launch_rows_t<L, SEG, CPL, MODE>(sys, P, x, O, st);
-    PE_CASE(1, MODE_EVAL)
-    PE_CASE(1, MODE_FONLY)
-    PE_CASE(2, MODE_EVAL)
-    PE_CASE(2, MODE_FONLY)
-    PE_CASE(4, MODE_EVAL)
-    PE_CASE(4, MODE_FONLY)
-    PE_CASE(8, MODE_EVAL)
-    PE_CASE(8, MODE_FONLY)
+  const int G = sys->plan.G;
+  switch ((G * 16 + sys->plan.cpl) * 4 + mode) {
+#define PE_CASE(G_, CPL, MODE) \
+  case (G_ * 16 + CPL) * 4 + MODE:  \
+    return launch_rows_t<L, SEG, CPL, G_, MODE>(sys, P, x, O, st);
+    PE_CASE(1, 1, MODE_EVAL)
+    PE_CASE(1, 1, MODE_FONLY)
+    PE_CASE(1, 2, MODE_EVAL)
+    PE_CASE(1, 2, MODE_FONLY)
+    PE_CASE(1, 4, MODE_EVAL)
+    PE_CASE(1, 4, MODE_FONLY)
+    PE_CASE(1, 8, MODE_EVAL)
+    PE_CASE(1, 8, MODE_FONLY)
 #undef PE_CASE
   }
   return hipErrorInvalidValue;
 }
 
+// the four-chunk workgroups exist for D and DD with up to 512 columns
 template <int L, int SEG>
-hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+hipError_t dispatch_rows_seg_g4(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
+                                hipStream_t st) {
+  switch (sys->plan.cpl * 4 + mode) {
+    case 1 * 4 + MODE_EVAL: return launch_rows_t<L, SEG, 1, 4, MODE_EVAL>(sys, P, x, O, st);
+    case 1 * 4 + MODE_FONLY: return launch_rows_t<L, SEG, 1, 4, MODE_FONLY>(sys, P, x, O, st);
+    case 2 * 4 + MODE_EVAL: return launch_rows_t<L, SEG, 2, 4, MODE_EVAL>(sys, P, x, O, st);
+    case 2 * 4 + MODE_FONLY: return launch_rows_t<L, SEG, 2, 4, MODE_FONLY>(sys, P, x, O, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L, int SEG>
+hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                             double* part, double* g, hipStream_t st) {
   switch (sys->plan.cpl) {
-    case 1: return launch_adj_t<L, SEG, 1>(sys, P, x, v, G, gsize, part, g, st);
-    case 2: return launch_adj_t<L, SEG, 2>(sys, P, x, v, G, gsize, part, g, st);
-    case 4: return launch_adj_t<L, SEG, 4>(sys, P, x, v, G, gsize, part, g, st);
-    case 8: return launch_adj_t<L, SEG, 8>(sys, P, x, v, G, gsize, part, g, st);
+    case 1: return launch_adj_t<L, SEG, 1>(sys, P, x, v, NG, gsize, part, g, st);
+    case 2: return launch_adj_t<L, SEG, 2>(sys, P, x, v, NG, gsize, part, g, st);
+    case 4: return launch_adj_t<L, SEG, 4>(sys, P, x, v, NG, gsize, part, g, st);
+    case 8: return launch_adj_t<L, SEG, 8>(sys, P, x, v, NG, gsize, part, g, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                          hipStream_t st) {
-  const int L = sys->level, seg = sys->plan.seg;
+  const int L = sys->level, seg = sys->plan.seg, G = sys->plan.G;
+  if (G == 4) {
+    if (L == 1 && seg == 8) return dispatch_rows_seg_g4<1, 8>(sys, P, x, O, mode, st);
+    if (L == 2 && seg == 4) return dispatch_rows_seg_g4<2, 4>(sys, P, x, O, mode, st);
+    return hipErrorInvalidValue;
+  }
   if (L == 1 && seg == 8) return dispatch_rows_seg<1, 8>(sys, P, x, O, mode, st);
   if (L == 2 && seg == 4) return dispatch_rows_seg<2, 4>(sys, P, x, O, mode, st);
   if (L == 4 && seg == 4) return dispatch_rows_seg<4, 4>(sys, P, x, O, mode, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int G, int gsize,
+hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
   const int L = sys->level, seg = sys->plan.seg;
-  if (L == 1 && seg == 8) return dispatch_adj_seg<1, 8>(sys, P, x, v, G, gsize, part, g, st);
-  if (L == 2 && seg == 4) return dispatch_adj_seg<2, 4>(sys, P, x, v, G, gsize, part, g, st);
-  if (L == 4 && seg == 4) return dispatch_adj_seg<4, 4>(sys, P, x, v, G, gsize, part, g, st);
+  if (L == 1 && seg == 8) return dispatch_adj_seg<1, 8>(sys, P, x, v, NG, gsize, part, g, st);
+  if (L == 2 && seg == 4) return dispatch_adj_seg<2, 4>(sys, P, x, v, NG, gsize, part, g, st);
+  if (L == 4 && seg == 4) return dispatch_adj_seg<4, 4>(sys, P, x, v, NG, gsize, part, g, st);
   return hipErrorInvalidValue;
 }
 
@@ -197,24 +217,29 @@ pe_status upload(pe_system* sys, const std::vector<T>& v, const T*& dst, hipStre
   return PE_OK;
 }
 
-pe_status choose_plan(pe_system* sys, int seg, int max_slots) {
+// Launch shape: G chunks at once (G = 4 needs at least two chunks in some
+// row, room in LDS for four slot regions and n + R <= 512 columns).
+pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   Packed& H = sys->host;
   Plan pl;
-  pl.T = kThreads;
   pl.seg = seg;
   pl.max_slots = std::max(H.max_slots_used, 1);
-  pl.cpl = cpl_bucket(H.ncols, pl.T);
+  pl.cpl = cpl_bucket(H.ncols, kSub);
   if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 columns (n + R) is not supported");
   const size_t limit = device_lds_limit();
   const int L = H.level;
+  auto lds_for = [&](int tab_last, int G) { return lds_bytes<1>(H.n, tab_last, pl.max_slots, H.R, G) * L; };
   pl.tab_last = 0;
-  if (H.emax - 1 >= 2) {
-    pl.tab_last = H.emax - 1;
-    if (lds_bytes<1>(H.n, pl.tab_last, pl.max_slots, H.R) * L > limit) pl.tab_last = 0;
-  }
-  pl.lds = lds_bytes<1>(H.n, pl.tab_last, pl.max_slots, H.R) * L;
+  if (H.emax - 1 >= 2 && lds_for(H.emax - 1, 1) <= limit) pl.tab_last = H.emax - 1;
+  int max_chunks = 0;
+  for (int p = 0; p < H.N; ++p) max_chunks = std::max<int>(max_chunks, H.chunk_ptr[p + 1] - H.chunk_ptr[p]);
+  pl.G = 1;
+  const bool g4_ok = L <= 2 && pl.cpl <= 2 && H.ncols * 3 <= pl.max_slots * 4 && lds_for(pl.tab_last, 4) <= limit;
+  if (force_G == 4 && !g4_ok) return fail(PE_EUNSUPPORTED, "four-chunk workgroups do not fit this system");
+  if (force_G == 4 || (force_G == 0 && g4_ok && max_chunks >= 2)) pl.G = 4;
+  pl.lds = lds_for(pl.tab_last, pl.G);
+  pl.lds1 = lds_for(pl.tab_last, 1);
   if (pl.lds > limit) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
-  (void)max_slots;
   sys->plan = pl;
   return PE_OK;
 }
@@ -245,7 +270,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
   in.exps = exps;
   in.coef = coef;
   PackParams pp;
-  pp.threads = kThreads;
+  pp.threads = kSub;
   pp.seg = (level == 1 || level == 2 || level == 4) ? default_seg(level) : 4;
   pp.max_slots = (level == 1 || level == 2 || level == 4) ? default_slots(level) : 2048;
   std::string msg;
@@ -257,7 +282,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
     return fail(st, msg);
   }
   sys->level = level;
-  pe_status ps = choose_plan(sys, pp.seg, pp.max_slots);
+  pe_status ps = choose_plan(sys, pp.seg, 0);
   if (ps != PE_OK) {
     delete sys;
     return ps;
@@ -360,8 +385,8 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
   const int target = 4096;
   int gsize = int(std::max<int64_t>(1, (int64_t(N) * P + target - 1) / target));
   gsize = std::min(gsize, N);
-  const int G = (N + gsize - 1) / gsize;
-  const size_t need = size_t(P) * G * 2 * L * n * sizeof(double);
+  const int NG = (N + gsize - 1) / gsize;
+  const size_t need = size_t(P) * NG * 2 * L * n * sizeof(double);
   double* part = nullptr;
   {
     std::lock_guard<std::mutex> lk(sys->ws_mu);
@@ -377,7 +402,7 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
     }
     part = static_cast<double*>(sys->adj_ws);
   }
-  hipError_t e = dispatch_adj(sys, P, x, v, G, gsize, part, g, hs);
+  hipError_t e = dispatch_adj(sys, P, x, v, NG, gsize, part, g, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
   return PE_OK;
 }
@@ -504,13 +529,13 @@ namespace {
 
 template <int L, int SEG, int CPL, int MODE>
 hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const BatchOut& out, hipStream_t st) {
-  auto kern = batch_rows_kernel<L, SEG, CPL, kThreads, MODE>;
+  auto kern = batch_rows_kernel<L, SEG, CPL, MODE>;
   if (b->lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds));
     if (e != hipSuccess) return e;
   }
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kThreads, b->lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kSub, b->lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -518,7 +543,7 @@ hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const Batch
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, b->nitems));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kThreads), b->lds, st, (const SysView*)b->d_views,
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kSub), b->lds, st, (const SysView*)b->d_views,
                      (const uint64_t*)b->d_items, b->nitems, b->d_counter, P, x, (const int64_t*)b->d_offs, out);
   return hipGetLastError();
 }
@@ -593,10 +618,10 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
       return fail(PE_EINVAL, "batched systems must share level, launch shape and device");
     }
     maxcols = std::max(maxcols, y->view.ncols);
-    b->lds = std::max(b->lds, y->plan.lds);
+    b->lds = std::max(b->lds, y->plan.lds1);
     b->maxN = std::max(b->maxN, y->view.N);
   }
-  b->cpl = cpl_bucket(maxcols, kThreads);
+  b->cpl = cpl_bucket(maxcols, kSub);
   const int L = b->level;
   // packed layout per point
   b->x_off.assign(S + 1, 0);
