@@ -95,8 +95,18 @@ pe_status pe_system_destroy(pe_system* sys);
 
 /* Sizes of a loaded system: info[0] = level, [1] = n, [2] = N, [3] = M,
  * [4] = nnz, [5] = largest exponent, [6] = largest monomial size k,
- * [7] = device bytes held. */
-pe_status pe_system_info(const pe_system* sys, int64_t info[8]);
+ * [7] = device bytes held, [8] = chunks per workgroup of the evaluation
+ * launch (1 or 4), [9] = LDS bytes per evaluation workgroup. */
+pe_status pe_system_info(const pe_system* sys, int64_t info[10]);
+
+/* Set the evaluation launch shape: each workgroup (256 threads per chunk)
+ * works on `chunks_per_workgroup` (1 or 4) chunks of a row at once and adds
+ * their partial rows in a fixed order; 0 restores the library's choice.
+ * Results are bitwise reproducible for a given shape; different shapes
+ * differ only by rounding.  PE_EUNSUPPORTED if the shape does not fit this
+ * system (LDS or column count); PE_EINVAL for other values.  Not to be
+ * called while work using the system is being enqueued. */
+pe_status pe_system_set_shape(pe_system* sys, int32_t chunks_per_workgroup);
 
 /* Evaluate F and J at P points (Sec. 2: power table, reverse-mode product
  * derivatives, coefficient/exponent multiplication and summation).

@@ -236,7 +236,7 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   pl.G = 1;
   const bool g4_ok = L <= 2 && pl.cpl <= 2 && H.ncols * 3 <= pl.max_slots * 4 && lds_for(pl.tab_last, 4) <= limit;
   if (force_G == 4 && !g4_ok) return fail(PE_EUNSUPPORTED, "four-chunk workgroups do not fit this system");
-  if (force_G == 4 || (force_G == 0 && g4_ok && max_chunks >= 2)) pl.G = 4;
+  if (force_G == 4 || (force_G == 0 && g4_ok && max_chunks >= 2)) pl.G = 4;  // force_G == 1 keeps 1
   pl.lds = lds_for(pl.tab_last, pl.G);
   pl.lds1 = lds_for(pl.tab_last, 1);
   if (pl.lds > limit) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
@@ -333,7 +333,7 @@ pe_status pe_system_destroy(pe_system* sys) {
   return PE_OK;
 }
 
-pe_status pe_system_info(const pe_system* sys, int64_t info[8]) {
+pe_status pe_system_info(const pe_system* sys, int64_t info[10]) {
   if (!sys || !info) return fail(PE_EINVAL, "NULL argument");
   const Packed& H = sys->host;
   info[0] = sys->level;
@@ -344,6 +344,23 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[8]) {
   info[5] = H.emax;
   info[6] = H.kmax;
   info[7] = int64_t(sys->device_bytes);
+  info[8] = sys->plan.G;
+  info[9] = int64_t(sys->plan.lds);
+  return PE_OK;
+}
+
+pe_status pe_system_set_shape(pe_system* sys, int32_t chunks_per_workgroup) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (chunks_per_workgroup != 0 && chunks_per_workgroup != 1 && chunks_per_workgroup != 4)
+    return fail(PE_EINVAL, "chunks_per_workgroup must be 0, 1 or 4");
+  Plan saved = sys->plan;
+  pe_status st = choose_plan(sys, sys->plan.seg, chunks_per_workgroup);
+  if (st != PE_OK) {
+    sys->plan = saved;
+    return st;
+  }
+  sys->view.tab_last = sys->plan.tab_last;
+  sys->view.max_slots = sys->plan.max_slots;
   return PE_OK;
 }
 

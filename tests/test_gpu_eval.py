@@ -174,11 +174,29 @@ def test_F_only_and_points(pe, L):
         assert eF <= tol
 
 
-def test_deterministic(pe):
+def test_deterministic_and_shapes(pe):
+    """Bitwise equal reruns for each launch shape; the one-chunk and
+    four-chunk workgroups differ only by rounding."""
+    import torch
     sys_, x = synth.workload("dd_n256")
-    F1, J1 = run_eval(pe, sys_, x)
-    F2, J2 = run_eval(pe, sys_, x)
-    assert np.array_equal(F1, F2) and np.array_equal(J1, J2)
+    S = pe.System.from_sparse(sys_)
+    assert S.info()["chunks_per_workgroup"] == 4
+    xd = U.to_device(x)
+    outs = {}
+    for G in (4, 1):
+        S.set_shape(G)
+        assert S.info()["chunks_per_workgroup"] == G
+        a = [t.cpu().numpy() for t in S.eval(xd)]
+        b = [t.cpu().numpy() for t in S.eval(xd)]
+        torch.cuda.synchronize()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), G
+        outs[G] = a
+    tol = U.tolerance(sys_)
+    rows = [0, 100, 255]
+    for G in (1, 4):
+        eF, eJ = U.max_errors_rows(sys_, x[0], outs[G][0][0], outs[G][1][0], rows, parallel=False)
+        assert eF <= tol and eJ <= tol, (G, eF, eJ)
+    S.close()
 
 
 @pytest.mark.parametrize("L", [1, 2, 4])
