@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512 "
                          "and dd_batch4096 print the same kind of line for context")
@@ -83,6 +85,15 @@ def main():
     from paper_1402_2626_amd import synth
     from paper_1402_2626_amd import workmodel as W
 
+    if args.copy_reference:
+        import torch
+        a = torch.ones(args.copy_reference << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": a.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.workload == "dd_batch4096":
         return bench_batch(args)
     if args.workload == "dd_adjoint_1024x512":
