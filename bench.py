@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
+    ap.add_argument("--shapes", action="store_true",
+                    help="time every compiled launch shape of the workload (one line each) and exit")
+    ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512 "
                          "and dd_batch4096 print the same kind of line for context")
@@ -113,6 +116,22 @@ def main():
 
     dev = torch.device("cuda:0")
     S = pe.System.from_sparse(sys_)
+    if args.shapes:
+        xd = torch.from_numpy(x).to(dev)
+        st = torch.cuda.current_stream()
+        for seg in (2, 4, 8, 16):
+            for G in (1, 2, 4):
+                try:
+                    S.set_shape(G, segment=seg)
+                except pe.PolyevalError:
+                    continue
+                dt, ms = _time_steps(lambda: S.eval(xd, stream=st), args.steps, args.warmup, st)
+                print(json.dumps({"workload": args.workload, "segment": seg, "chunks_per_workgroup": G,
+                                  "kernel_ms": ms, "step_ms": dt / args.steps * 1e3,
+                                  "lds_bytes": S.info()["lds_bytes"]}), flush=True)
+        return
+    if args.autotune:
+        S.autotune(P)
     xd = torch.from_numpy(x).to(dev)
     F = torch.empty((P, 2, sys_.level, sys_.n_polys), dtype=torch.float64, device=dev)
     J = torch.empty((P, 2, sys_.level, sys_.n_polys, sys_.n_vars), dtype=torch.float64, device=dev)

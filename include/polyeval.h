@@ -96,17 +96,26 @@ pe_status pe_system_destroy(pe_system* sys);
 /* Sizes of a loaded system: info[0] = level, [1] = n, [2] = N, [3] = M,
  * [4] = nnz, [5] = largest exponent, [6] = largest monomial size k,
  * [7] = device bytes held, [8] = chunks per workgroup of the evaluation
- * launch (1 or 4), [9] = LDS bytes per evaluation workgroup. */
-pe_status pe_system_info(const pe_system* sys, int64_t info[10]);
+ * launch, [9] = LDS bytes per evaluation workgroup, [10] = segment length
+ * (variables per lane). */
+pe_status pe_system_info(const pe_system* sys, int64_t info[11]);
 
-/* Set the evaluation launch shape: each workgroup (256 threads per chunk)
- * works on `chunks_per_workgroup` (1 or 4) chunks of a row at once and adds
- * their partial rows in a fixed order; 0 restores the library's choice.
- * Results are bitwise reproducible for a given shape; different shapes
- * differ only by rounding.  PE_EUNSUPPORTED if the shape does not fit this
- * system (LDS or column count); PE_EINVAL for other values.  Not to be
- * called while work using the system is being enqueued. */
-pe_status pe_system_set_shape(pe_system* sys, int32_t chunks_per_workgroup);
+/* Set the evaluation launch shape.  A monomial of k variables is handled by
+ * s lanes (s the smallest power of two with s * segment >= k); the
+ * monomials of a row are cut into chunks of 256 lanes, and a workgroup of
+ * chunks_per_workgroup * 256 threads works on that many chunks of a row at
+ * once, adding their partial rows in a fixed order.
+ *   segment               variables per lane: 8 or 16 (D), 4 or 8 (DD),
+ *                         2 or 4 (QD); 0 = the level's default.
+ *   chunks_per_workgroup  1, 2 or 4 as compiled for the level and segment;
+ *                         0 = the largest that fits.
+ * A new segment length repacks the system (host work and a device upload
+ * on `stream`, which is synchronised).  Results are bitwise reproducible for
+ * a given shape; shapes differ only by rounding.  PE_EUNSUPPORTED if the
+ * shape is not compiled or does not fit (LDS, column count); the previous
+ * shape is then kept.  Not to be called while work using the system is
+ * enqueued. */
+pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_per_workgroup, void* stream);
 
 /* Evaluate F and J at P points (Sec. 2: power table, reverse-mode product
  * derivatives, coefficient/exponent multiplication and summation).
@@ -180,9 +189,10 @@ pe_status pe_batch_newton_step(const pe_batch* batch, int32_t P, double* x_inout
  * file if one is set. */
 pe_status pe_autotune(pe_system* sys, int32_t P, void* stream);
 
-/* Use `path` (NULL to disable) as a plan cache: a text file of tuned launch
- * shapes keyed by level and system shape, read when systems are created and
- * appended to by pe_autotune. */
+/* Use `path` (NULL to disable) as a plan cache: a text file with one line
+ * per tuned system, "<key> | <segment> <chunks_per_workgroup> <microseconds>",
+ * the key made of level, n, N, M, nnz, largest k and largest exponent.
+ * pe_system_create uses the last matching line; pe_autotune appends. */
 pe_status pe_set_plan_cache(const char* path);
 
 #ifdef __cplusplus

@@ -339,11 +339,16 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    C<L> f = load_aos<L>(fpart);
-    for (int r = 1; r < S.R; ++r) f = c_add(f, load_aos<L>(fpart + size_t(r) * (2 * L)));
-    if (O.f_sign < 0) f = c_neg(f);
-    store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, f);
+  // F = sum of the R partial columns, added pairwise across the lanes of the
+  // first wavefront (R <= 32)
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    C<L> f = r < S.R ? load_aos<L>(fpart + size_t(r) * (2 * L)) : c_zero<L>();
+    for (int m = 1; m < 32; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
+    if (r == 0) {
+      if (O.f_sign < 0) f = c_neg(f);
+      store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, f);
+    }
   }
   __syncthreads();
 }

@@ -82,6 +82,11 @@ struct Plan {
 struct pe_system {
   int device = 0;
   int level = 0;
+  int n_vars = 0;
+  // the input as given (host copy), for repacking with another launch shape
+  std::vector<int64_t> in_poly_ptr, in_mon_ptr;
+  std::vector<int32_t> in_var, in_exp;
+  std::vector<double> in_coef;
   Packed host;  // kept for batches and tuning (structure only)
   Plan plan;
   SysView view{};
@@ -131,37 +136,21 @@ hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const doub
   return hipGetLastError();
 }
 
-// dispatch over (G, CPL, MODE) for a level
-template <int L, int SEG>
-hipError_t dispatch_rows_seg(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
+// dispatch over (CPL, MODE) for one compiled (L, SEG, G)
+template <int L, int SEG, int G>
+hipError_t dispatch_rows_lsg(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                              hipStream_t st) {
-  const int G = sys->plan.G;
-  switch ((G * 16 + sys->plan.cpl) * 4 + mode) {
-#define PE_CASE(G_, CPL, MODE) \
-  case (G_ * 16 + CPL) * 4 + MODE:  \
-    return launch_rows_t<L, SEG, CPL, G_, MODE>(sys, P, x, O, st);
-    PE_CASE(1, 1, MODE_EVAL)
-    PE_CASE(1, 1, MODE_FONLY)
-    PE_CASE(1, 2, MODE_EVAL)
-    PE_CASE(1, 2, MODE_FONLY)
-    PE_CASE(1, 4, MODE_EVAL)
-    PE_CASE(1, 4, MODE_FONLY)
-    PE_CASE(1, 8, MODE_EVAL)
-    PE_CASE(1, 8, MODE_FONLY)
-#undef PE_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-// the four-chunk workgroups exist for D and DD with up to 512 columns
-template <int L, int SEG>
-hipError_t dispatch_rows_seg_g4(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
-                                hipStream_t st) {
-  switch (sys->plan.cpl * 4 + mode) {
-    case 1 * 4 + MODE_EVAL: return launch_rows_t<L, SEG, 1, 4, MODE_EVAL>(sys, P, x, O, st);
-    case 1 * 4 + MODE_FONLY: return launch_rows_t<L, SEG, 1, 4, MODE_FONLY>(sys, P, x, O, st);
-    case 2 * 4 + MODE_EVAL: return launch_rows_t<L, SEG, 2, 4, MODE_EVAL>(sys, P, x, O, st);
-    case 2 * 4 + MODE_FONLY: return launch_rows_t<L, SEG, 2, 4, MODE_FONLY>(sys, P, x, O, st);
+  const int cpl = sys->plan.cpl;
+  if (mode == MODE_EVAL) {
+    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_EVAL>(sys, P, x, O, st);
+    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_EVAL>(sys, P, x, O, st);
+    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_EVAL>(sys, P, x, O, st);
+    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_EVAL>(sys, P, x, O, st);
+  } else {
+    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_FONLY>(sys, P, x, O, st);
+    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_FONLY>(sys, P, x, O, st);
+    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_FONLY>(sys, P, x, O, st);
+    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_FONLY>(sys, P, x, O, st);
   }
   return hipErrorInvalidValue;
 }
@@ -178,26 +167,46 @@ hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const 
   return hipErrorInvalidValue;
 }
 
+// The compiled launch shapes (level, segment length, chunks per workgroup).
+// A workgroup of G chunks has G * 256 threads; G > 1 is compiled for up to
+// 512 columns only.
+#define PE_SHAPES(X) \
+  X(1, 8, 1)         \
+  X(1, 8, 4)         \
+  X(1, 16, 1)        \
+  X(1, 16, 2)        \
+  X(2, 4, 1)         \
+  X(2, 4, 4)         \
+  X(2, 8, 1)         \
+  X(2, 8, 2)         \
+  X(4, 4, 1)         \
+  X(4, 2, 1)
+
+bool shape_compiled(int L, int seg, int G) {
+#define PE_X(L_, S_, G_) \
+  if (L == L_ && seg == S_ && G == G_) return true;
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return false;
+}
+
 hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                          hipStream_t st) {
   const int L = sys->level, seg = sys->plan.seg, G = sys->plan.G;
-  if (G == 4) {
-    if (L == 1 && seg == 8) return dispatch_rows_seg_g4<1, 8>(sys, P, x, O, mode, st);
-    if (L == 2 && seg == 4) return dispatch_rows_seg_g4<2, 4>(sys, P, x, O, mode, st);
-    return hipErrorInvalidValue;
-  }
-  if (L == 1 && seg == 8) return dispatch_rows_seg<1, 8>(sys, P, x, O, mode, st);
-  if (L == 2 && seg == 4) return dispatch_rows_seg<2, 4>(sys, P, x, O, mode, st);
-  if (L == 4 && seg == 4) return dispatch_rows_seg<4, 4>(sys, P, x, O, mode, st);
+#define PE_X(L_, S_, G_) \
+  if (L == L_ && seg == S_ && G == G_) return dispatch_rows_lsg<L_, S_, G_>(sys, P, x, O, mode, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
   return hipErrorInvalidValue;
 }
 
 hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
   const int L = sys->level, seg = sys->plan.seg;
-  if (L == 1 && seg == 8) return dispatch_adj_seg<1, 8>(sys, P, x, v, NG, gsize, part, g, st);
-  if (L == 2 && seg == 4) return dispatch_adj_seg<2, 4>(sys, P, x, v, NG, gsize, part, g, st);
-  if (L == 4 && seg == 4) return dispatch_adj_seg<4, 4>(sys, P, x, v, NG, gsize, part, g, st);
+#define PE_X(L_, S_, G_) \
+  if (G_ == 1 && L == L_ && seg == S_) return dispatch_adj_seg<L_, S_>(sys, P, x, v, NG, gsize, part, g, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
   return hipErrorInvalidValue;
 }
 
@@ -217,8 +226,9 @@ pe_status upload(pe_system* sys, const std::vector<T>& v, const T*& dst, hipStre
   return PE_OK;
 }
 
-// Launch shape: G chunks at once (G = 4 needs at least two chunks in some
-// row, room in LDS for four slot regions and n + R <= 512 columns).
+// Launch shape for a packed system: G chunks at once (G > 1 needs at least
+// two chunks in some row, room in LDS for G slot regions and at most 512
+// columns).  force_G = 0 picks the largest fitting G of the compiled shapes.
 pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   Packed& H = sys->host;
   Plan pl;
@@ -233,15 +243,137 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   if (H.emax - 1 >= 2 && lds_for(H.emax - 1, 1) <= limit) pl.tab_last = H.emax - 1;
   int max_chunks = 0;
   for (int p = 0; p < H.N; ++p) max_chunks = std::max<int>(max_chunks, H.chunk_ptr[p + 1] - H.chunk_ptr[p]);
-  pl.G = 1;
-  const bool g4_ok = L <= 2 && pl.cpl <= 2 && H.ncols * 3 <= pl.max_slots * 4 && lds_for(pl.tab_last, 4) <= limit;
-  if (force_G == 4 && !g4_ok) return fail(PE_EUNSUPPORTED, "four-chunk workgroups do not fit this system");
-  if (force_G == 4 || (force_G == 0 && g4_ok && max_chunks >= 2)) pl.G = 4;  // force_G == 1 keeps 1
+  auto fits = [&](int G) {
+    if (!shape_compiled(L, seg, G)) return false;
+    if (G == 1) return true;
+    return pl.cpl <= 2 && H.ncols * (G - 1) <= pl.max_slots * G && lds_for(pl.tab_last, G) <= limit;
+  };
+  if (force_G > 0) {
+    if (!fits(force_G)) return fail(PE_EUNSUPPORTED, "this launch shape does not fit the system");
+    pl.G = force_G;
+  } else {
+    pl.G = 1;
+    for (int G : {4, 2})
+      if (max_chunks >= 2 && fits(G)) {
+        pl.G = G;
+        break;
+      }
+  }
   pl.lds = lds_for(pl.tab_last, pl.G);
   pl.lds1 = lds_for(pl.tab_last, 1);
   if (pl.lds > limit) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
   sys->plan = pl;
   return PE_OK;
+}
+
+// slot budget of a chunk: about 36 KB (D, DD; 70 KB with long segments) or
+// 68 KB (QD) of LDS
+int slots_for(int L, int seg) {
+  if (L == 4) return 1088;
+  const int bytes = (seg >= 8 && !(L == 1 && seg == 8)) ? 70 * 1024 : 36 * 1024;
+  return std::max(kMaxMonomialVars + 1, bytes / (16 * L));
+}
+
+void free_device(pe_system* sys) {
+  for (void* p : sys->allocs) (void)hipFree(p);
+  sys->allocs.clear();
+  sys->device_bytes = 0;
+}
+
+// (Re)pack the stored input for segment length `seg`, choose G and upload.
+pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) {
+  SysInput in;
+  in.level = sys->level;
+  in.n_vars = sys->n_vars;
+  in.n_polys = int(sys->in_poly_ptr.size()) - 1;
+  in.poly_ptr = sys->in_poly_ptr.data();
+  in.mon_ptr = sys->in_mon_ptr.data();
+  in.var_idx = sys->in_var.data();
+  in.exps = sys->in_exp.data();
+  in.coef = sys->in_coef.data();
+  PackParams pp;
+  pp.threads = kSub;
+  pp.seg = seg;
+  pp.max_slots = slots_for(sys->level, seg);
+  Packed H;
+  std::string msg;
+  int st = pack_system(in, pp, H, msg);
+  if (st != kOk) return fail(st, msg);
+  Packed saved_host = std::move(sys->host);
+  Plan saved_plan = sys->plan;
+  sys->host = std::move(H);
+  pe_status ps = choose_plan(sys, seg, force_G);
+  if (ps != PE_OK) {
+    sys->host = std::move(saved_host);
+    sys->plan = saved_plan;
+    return ps;
+  }
+  free_device(sys);
+  const Packed& P = sys->host;
+  SysView& V = sys->view;
+  V = SysView{};
+  V.n = P.n;
+  V.N = P.N;
+  V.R = P.R;
+  V.ncols = P.ncols;
+  V.emax = P.emax;
+  V.tab_last = sys->plan.tab_last;
+  V.max_slots = sys->plan.max_slots;
+  pe_status e = PE_OK;
+  if ((e = upload(sys, P.chunks, V.chunks, hs)) != PE_OK || (e = upload(sys, P.chunk_ptr, V.chunk_ptr, hs)) != PE_OK ||
+      (e = upload(sys, P.occ, V.occ, hs)) != PE_OK || (e = upload(sys, P.mcoef, V.mcoef, hs)) != PE_OK ||
+      (e = upload(sys, P.mmeta, V.mmeta, hs)) != PE_OK || (e = upload(sys, P.colptr, V.colptr, hs)) != PE_OK)
+    return e;
+  PE_HIP(hipStreamSynchronize(hs));
+  // the device copies are authoritative; keep only what batches and tuning need
+  sys->host.occ.clear();
+  sys->host.occ.shrink_to_fit();
+  sys->host.mcoef.clear();
+  sys->host.mcoef.shrink_to_fit();
+  sys->host.colptr.clear();
+  sys->host.colptr.shrink_to_fit();
+  return PE_OK;
+}
+
+// ------------------------------------------------------------------ plan cache
+
+std::mutex g_cache_mu;
+std::string g_cache_path;
+
+std::string plan_key(const pe_system* sys) {
+  const Packed& H = sys->host;
+  std::ostringstream k;
+  k << "L" << sys->level << " n" << H.n << " N" << H.N << " M" << H.M << " nnz" << H.nnz << " kmax" << H.kmax
+    << " emax" << H.emax;
+  return k.str();
+}
+
+// returns true and the shape if the cache has an entry for this system
+bool cache_lookup(const std::string& key, int& seg, int& G) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache_path.empty()) return false;
+  std::ifstream f(g_cache_path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const size_t bar = line.find(" | ");
+    if (bar == std::string::npos || line.compare(0, bar, key) != 0) continue;
+    std::istringstream r(line.substr(bar + 3));
+    int a = 0, b = 0;
+    if (r >> a >> b) {
+      seg = a;
+      G = b;
+      found = true;  // the last entry wins
+    }
+  }
+  return found;
+}
+
+void cache_store(const std::string& key, int seg, int G, double us) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache_path.empty()) return;
+  std::ofstream f(g_cache_path, std::ios::app);
+  f << key << " | " << seg << " " << G << " " << us << "\n";
 }
 
 }  // namespace
@@ -269,71 +401,59 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
   in.var_idx = var_idx;
   in.exps = exps;
   in.coef = coef;
-  PackParams pp;
-  pp.threads = kSub;
-  pp.seg = (level == 1 || level == 2 || level == 4) ? default_seg(level) : 4;
-  pp.max_slots = (level == 1 || level == 2 || level == 4) ? default_slots(level) : 2048;
   std::string msg;
+  int st = validate(in, msg);
+  if (st != kOk) return fail(st, msg);
   auto* sys = new (std::nothrow) pe_system();
   if (!sys) return fail(PE_ENOMEM, "host allocation failed");
-  int st = pack_system(in, pp, sys->host, msg);
-  if (st != kOk) {
-    delete sys;
-    return fail(st, msg);
-  }
   sys->level = level;
-  pe_status ps = choose_plan(sys, pp.seg, 0);
-  if (ps != PE_OK) {
+  sys->n_vars = n_vars;
+  const int64_t M = poly_ptr[n_polys];
+  const int64_t nnz = M > 0 ? mon_ptr[M] : 0;
+  try {
+    sys->in_poly_ptr.assign(poly_ptr, poly_ptr + n_polys + 1);
+    if (M > 0) sys->in_mon_ptr.assign(mon_ptr, mon_ptr + M + 1);
+    else sys->in_mon_ptr.assign(1, 0);
+    sys->in_var.assign(var_idx, var_idx + nnz);
+    sys->in_exp.assign(exps, exps + nnz);
+    sys->in_coef.assign(coef, coef + size_t(M) * 2 * level);
+  } catch (...) {
     delete sys;
-    return ps;
+    return fail(PE_ENOMEM, "host allocation failed");
   }
   hipError_t he = hipGetDevice(&sys->device);
   if (he != hipSuccess) {
     delete sys;
     return fail(PE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
   }
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  const Packed& H = sys->host;
-  SysView& V = sys->view;
-  V.n = H.n;
-  V.N = H.N;
-  V.R = H.R;
-  V.ncols = H.ncols;
-  V.emax = H.emax;
-  V.tab_last = sys->plan.tab_last;
-  V.max_slots = sys->plan.max_slots;
-  pe_status e = PE_OK;
-  if ((e = upload(sys, H.chunks, V.chunks, hs)) != PE_OK || (e = upload(sys, H.chunk_ptr, V.chunk_ptr, hs)) != PE_OK ||
-      (e = upload(sys, H.occ, V.occ, hs)) != PE_OK || (e = upload(sys, H.mcoef, V.mcoef, hs)) != PE_OK ||
-      (e = upload(sys, H.mmeta, V.mmeta, hs)) != PE_OK || (e = upload(sys, H.colptr, V.colptr, hs)) != PE_OK) {
-    pe_system_destroy(sys);
-    return e;
+  // launch shape: from the plan cache if it knows this system, else the default
+  int seg = default_seg(level), G = 0;
+  pe_status ps = pack_and_upload(sys, seg, G, static_cast<hipStream_t>(stream));
+  if (ps == PE_OK) {
+    int cseg = 0, cG = 0;
+    if (cache_lookup(plan_key(sys), cseg, cG) && (cseg != seg || cG != sys->plan.G))
+      if (pack_and_upload(sys, cseg, cG, static_cast<hipStream_t>(stream)) != PE_OK)
+        ps = pack_and_upload(sys, seg, G, static_cast<hipStream_t>(stream));
   }
-  he = hipStreamSynchronize(hs);
-  if (he != hipSuccess) {
+  if (ps != PE_OK) {
+    std::string keep = g_last_error;
     pe_system_destroy(sys);
-    return fail(PE_EDEVICE, std::string("upload: ") + hipGetErrorString(he));
+    g_last_error = keep;
+    return ps;
   }
-  // the device copies are authoritative; keep only what batches and tuning need
-  sys->host.occ.clear();
-  sys->host.occ.shrink_to_fit();
-  sys->host.mcoef.clear();
-  sys->host.mcoef.shrink_to_fit();
-  sys->host.colptr.clear();
-  sys->host.colptr.shrink_to_fit();
   *out = sys;
   return PE_OK;
 }
 
 pe_status pe_system_destroy(pe_system* sys) {
   if (!sys) return PE_OK;
-  for (void* p : sys->allocs) (void)hipFree(p);
+  free_device(sys);
   if (sys->adj_ws) (void)hipFree(sys->adj_ws);
   delete sys;
   return PE_OK;
 }
 
-pe_status pe_system_info(const pe_system* sys, int64_t info[10]) {
+pe_status pe_system_info(const pe_system* sys, int64_t info[11]) {
   if (!sys || !info) return fail(PE_EINVAL, "NULL argument");
   const Packed& H = sys->host;
   info[0] = sys->level;
@@ -346,22 +466,38 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[10]) {
   info[7] = int64_t(sys->device_bytes);
   info[8] = sys->plan.G;
   info[9] = int64_t(sys->plan.lds);
+  info[10] = sys->plan.seg;
   return PE_OK;
 }
 
-pe_status pe_system_set_shape(pe_system* sys, int32_t chunks_per_workgroup) {
+pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_per_workgroup, void* stream) {
   if (!sys) return fail(PE_EINVAL, "system is NULL");
-  if (chunks_per_workgroup != 0 && chunks_per_workgroup != 1 && chunks_per_workgroup != 4)
-    return fail(PE_EINVAL, "chunks_per_workgroup must be 0, 1 or 4");
-  Plan saved = sys->plan;
-  pe_status st = choose_plan(sys, sys->plan.seg, chunks_per_workgroup);
-  if (st != PE_OK) {
-    sys->plan = saved;
-    return st;
+  if (chunks_per_workgroup < 0 || chunks_per_workgroup > 4 || chunks_per_workgroup == 3 || segment < 0)
+    return fail(PE_EINVAL, "invalid launch shape");
+  const int seg = segment ? segment : default_seg(sys->level);
+  if (!shape_compiled(sys->level, seg, chunks_per_workgroup ? chunks_per_workgroup : 1))
+    return fail(PE_EUNSUPPORTED, "launch shape not compiled for this level");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (seg == sys->plan.seg) {
+    Plan saved = sys->plan;
+    pe_status st = choose_plan(sys, seg, chunks_per_workgroup);
+    if (st != PE_OK) {
+      sys->plan = saved;
+      return st;
+    }
+    sys->view.tab_last = sys->plan.tab_last;
+    sys->view.max_slots = sys->plan.max_slots;
+    return PE_OK;
   }
-  sys->view.tab_last = sys->plan.tab_last;
-  sys->view.max_slots = sys->plan.max_slots;
-  return PE_OK;
+  PE_HIP(hipStreamSynchronize(hs));
+  const int old_seg = sys->plan.seg, old_G = sys->plan.G;
+  pe_status st = pack_and_upload(sys, seg, chunks_per_workgroup, hs);
+  if (st != PE_OK) {
+    std::string keep = g_last_error;
+    if (pack_and_upload(sys, old_seg, old_G, hs) != PE_OK) keep += "; restoring the previous shape failed too";
+    g_last_error = keep;
+  }
+  return st;
 }
 
 pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, double* J, void* stream) {
@@ -586,9 +722,11 @@ hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const B
 }
 
 hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
-  if (b->level == 1 && b->seg == 8) return dispatch_batch_seg<1, 8>(b, P, x, out, mode, st);
-  if (b->level == 2 && b->seg == 4) return dispatch_batch_seg<2, 4>(b, P, x, out, mode, st);
-  if (b->level == 4 && b->seg == 4) return dispatch_batch_seg<4, 4>(b, P, x, out, mode, st);
+  const int L = b->level, seg = b->seg;
+#define PE_X(L_, S_, G_) \
+  if (G_ == 1 && L == L_ && seg == S_) return dispatch_batch_seg<L_, S_>(b, P, x, out, mode, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
   return hipErrorInvalidValue;
 }
 
@@ -790,7 +928,76 @@ pe_status pe_batch_newton_step(const pe_batch* b, int32_t P, double* x_inout, vo
   return PE_OK;
 }
 
-pe_status pe_autotune(pe_system*, int32_t, void*) { return PE_OK; }
-pe_status pe_set_plan_cache(const char*) { return PE_OK; }
+pe_status pe_autotune(pe_system* sys, int32_t P, void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (P < 1) return fail(PE_EINVAL, "P must be positive");
+  if (sys->view.N == 0) return PE_OK;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  // inputs: unit-modulus points; outputs F and J
+  const size_t xs = size_t(P) * 2 * L * n, fs = size_t(P) * 2 * L * N, js = fs * n;
+  std::vector<double> hx(xs, 0.0);
+  for (int pt = 0; pt < P; ++pt)
+    for (int j = 0; j < n; ++j) {
+      const double t = 0.7 + 0.013 * j + 0.1 * pt;
+      hx[(size_t(pt) * 2 * L + 0) * n + j] = std::cos(t);
+      hx[(size_t(pt) * 2 * L + L) * n + j] = std::sin(t);
+    }
+  double *dx = nullptr, *dF = nullptr, *dJ = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (dx) (void)hipFree(dx);
+    if (dF) (void)hipFree(dF);
+    if (dJ) (void)hipFree(dJ);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t he = hipMalloc(&dx, xs * 8);
+  if (he == hipSuccess) he = hipMalloc(&dF, fs * 8);
+  if (he == hipSuccess) he = hipMalloc(&dJ, js * 8);
+  if (he == hipSuccess) he = hipMemcpyAsync(dx, hx.data(), xs * 8, hipMemcpyHostToDevice, hs);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    cleanup();
+    return fail(PE_EDEVICE, std::string("autotune setup: ") + hipGetErrorString(he));
+  }
+  const int best_seg0 = sys->plan.seg, best_G0 = sys->plan.G;
+  int best_seg = best_seg0, best_G = best_G0;
+  double best_us = 1e300;
+  for (int seg : {1, 2, 4, 8, 16})
+    for (int G : {1, 2, 4}) {
+      if (!shape_compiled(L, seg, G)) continue;
+      if (pe_system_set_shape(sys, seg, G, stream) != PE_OK) continue;
+      double us = 1e300;
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)pe_eval(sys, P, dx, dF, dJ, stream);
+        (void)hipEventRecord(e0, hs);
+        const int iters = 5;
+        for (int it = 0; it < iters; ++it) (void)pe_eval(sys, P, dx, dF, dJ, stream);
+        (void)hipEventRecord(e1, hs);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        us = std::min(us, 1e3 * ms / iters);
+      }
+      if (us < best_us) {
+        best_us = us;
+        best_seg = seg;
+        best_G = G;
+      }
+    }
+  cleanup();
+  pe_status st = pe_system_set_shape(sys, best_seg, best_G, stream);
+  if (st != PE_OK) return st;
+  cache_store(plan_key(sys), best_seg, best_G, best_us);
+  return PE_OK;
+}
+
+pe_status pe_set_plan_cache(const char* path) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache_path = path ? path : "";
+  return PE_OK;
+}
 
 }  // extern "C"

@@ -35,7 +35,7 @@ SIGNATURES = {
     "pe_system_create": (_c_int, [ctypes.POINTER(_p), _c_int, _c_int, _c_int, _p, _p, _p, _p, _p, _p]),
     "pe_system_destroy": (_c_int, [_p]),
     "pe_system_info": (_c_int, [_p, _p]),
-    "pe_system_set_shape": (_c_int, [_p, _c_int]),
+    "pe_system_set_shape": (_c_int, [_p, _c_int, _c_int, _p]),
     "pe_eval": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_eval_adjoint": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_batch_create": (_c_int, [ctypes.POINTER(_p), _c_int, _p, _p]),
@@ -113,15 +113,17 @@ class System:
         return self._h
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 10)()
+        buf = (ctypes.c_int64 * 11)()
         _check(_lib.pe_system_info(self._h, buf), "pe_system_info")
         keys = ("level", "n", "N", "M", "nnz", "emax", "kmax", "device_bytes", "chunks_per_workgroup",
-                "lds_bytes")
+                "lds_bytes", "segment")
         return dict(zip(keys, list(buf)))
 
-    def set_shape(self, chunks_per_workgroup: int):
-        """1 or 4 chunks per workgroup (0: the library's choice)."""
-        _check(_lib.pe_system_set_shape(self._h, int(chunks_per_workgroup)), "pe_system_set_shape")
+    def set_shape(self, chunks_per_workgroup: int = 0, segment: int = 0, stream=None):
+        """Launch shape: chunks per workgroup (1, 2, 4; 0 = largest fitting)
+        and variables per lane (0 = the level's default)."""
+        _check(_lib.pe_system_set_shape(self._h, int(segment), int(chunks_per_workgroup), _stream(stream)),
+               "pe_system_set_shape")
 
     def close(self):
         if getattr(self, "_h", None):

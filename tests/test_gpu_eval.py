@@ -214,3 +214,50 @@ def test_cyclic_roots_closed_forms(pe, L):
     want_J = np.repeat(np.arange(1, n + 1, dtype=float)[:, None], n, axis=1)
     want_J[-1] = 1.0
     assert np.array_equal(J[0, 0, 0], want_J) and np.all(J[0, 1] == 0)
+
+
+def test_shapes_and_autotune(pe, tmp_path):
+    """Every compiled launch shape gives results within tolerance; autotune
+    keeps one of them and records it in the plan cache, which a new system
+    of the same shape picks up."""
+    import torch
+    sys_ = synth.random_system(41, 2, n_vars=96, n_polys=40, m=96, k=12, exp_lo=1, exp_hi=4)
+    x = synth.unit_circle_points(synth.rng_for(42), 2, 96, 2)
+    S = pe.System.from_sparse(sys_)
+    xd = U.to_device(x)
+    tol = U.tolerance(sys_)
+    seen = []
+    for seg in (4, 8):
+        for G in (1, 2, 4):
+            try:
+                S.set_shape(G, segment=seg)
+            except pe.PolyevalError as e:
+                assert e.status == pe.PE_EUNSUPPORTED
+                continue
+            info = S.info()
+            assert (info["segment"], info["chunks_per_workgroup"]) == (seg, G)
+            F, J = S.eval(xd)
+            torch.cuda.synchronize()
+            F, J = F.cpu().numpy(), J.cpu().numpy()
+            eF, eJ = U.max_errors_rows(sys_, x[1], F[1], J[1], [0, 17, 39], parallel=False)
+            assert eF <= tol and eJ <= tol, (seg, G, eF, eJ)
+            seen.append((seg, G))
+    assert (4, 1) in seen and (8, 1) in seen and len(seen) >= 3
+    cache = tmp_path / "plans.txt"
+    pe.set_plan_cache(str(cache))
+    try:
+        S.autotune(P=2)
+        chosen = S.info()
+        lines = cache.read_text().strip().splitlines()
+        assert len(lines) == 1 and f"| {chosen['segment']} {chosen['chunks_per_workgroup']} " in lines[0]
+        S2 = pe.System.from_sparse(sys_)
+        i2 = S2.info()
+        assert (i2["segment"], i2["chunks_per_workgroup"]) == (chosen["segment"], chosen["chunks_per_workgroup"])
+        F, J = S2.eval(xd)
+        torch.cuda.synchronize()
+        eF, eJ = U.max_errors_rows(sys_, x[0], F.cpu().numpy()[0], J.cpu().numpy()[0], [5], parallel=False)
+        assert eF <= tol and eJ <= tol
+        S2.close()
+    finally:
+        pe.set_plan_cache(None)
+    S.close()
