@@ -40,9 +40,9 @@ enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2 };
 struct SysView {
   int n, N, R, ncols;
   int emax;
-  int tab_last;  // powers 2..tab_last are in the LDS table (tab_last < 2: none)
+  int tab_first;  // powers tab_first..tab_last of every variable are in the
+  int tab_last;   // LDS table (tab_first = 1: x itself too; none if last < first)
   int max_slots;
-  int pad;
   const ChunkDesc* chunks;
   const uint32_t* chunk_ptr;
   const OccRec* occ;
@@ -127,23 +127,37 @@ __device__ C<L> c_pow(const C<L>& x, int e) {
   return r;
 }
 
-// x^e (e >= 2) from the LDS table or by powering
+__device__ __forceinline__ int tab_entries(const SysView& S) {
+  return S.tab_last >= S.tab_first ? S.tab_last - S.tab_first + 1 : 0;
+}
+
+// x^e (e >= 2) from the LDS table, from the table's highest power times x,
+// or by binary powering
 template <int L>
 __device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, int v, int e, const C<L>& xv) {
-  if (e <= S.tab_last) return load_aos<L>(tab + (size_t(e - 2) * S.n + v) * (2 * L));
+  if (e >= S.tab_first && e <= S.tab_last) return load_aos<L>(tab + (size_t(e - S.tab_first) * S.n + v) * (2 * L));
+  if (e == S.tab_last + 1 && S.tab_last >= S.tab_first && S.tab_last >= 2)
+    return c_mul(load_aos<L>(tab + (size_t(S.tab_last - S.tab_first) * S.n + v) * (2 * L)), xv);
   return c_pow(xv, e);
 }
 
-// Build the power table x_v^e, e = 2..tab_last, for the point in LDS.
+// x_v for a gathered variable: from the LDS table when it holds x
+template <int L>
+__device__ __forceinline__ C<L> load_x(const SysView& S, const double* __restrict__ xpt, const double* tab, int v) {
+  if (S.tab_first == 1 && S.tab_last >= 1) return load_aos<L>(tab + size_t(v) * (2 * L));
+  return load_planar<L>(xpt, S.n, v);
+}
+
+// Build the power table x_v^e, e = tab_first..tab_last, for the point in LDS.
 template <int L, int T>
 __device__ void build_power_table(const SysView& S, const double* __restrict__ xpt, double* tab) {
-  if (S.tab_last < 2) return;
+  if (tab_entries(S) == 0) return;
   for (int v = threadIdx.x; v < S.n; v += T) {
-    C<L> x1 = load_planar<L>(xpt, S.n, v);
+    const C<L> x1 = load_planar<L>(xpt, S.n, v);
     C<L> p = x1;
-    for (int e = 2; e <= S.tab_last; ++e) {
-      p = c_mul(p, x1);
-      store_aos(tab + (size_t(e - 2) * S.n + v) * (2 * L), p);
+    for (int e = 1; e <= S.tab_last; ++e) {
+      if (e > 1) p = c_mul(p, x1);
+      if (e >= S.tab_first) store_aos(tab + (size_t(e - S.tab_first) * S.n + v) * (2 * L), p);
     }
   }
 }
@@ -196,7 +210,7 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
     if (i < len) {
       const OccRec r = S.occ[cd.occ_base + size_t(i) * cd.width + lt];
       const int v = r.var, d = r.exp;
-      xv[i] = load_planar<L>(xpt, S.n, v);
+      xv[i] = load_x<L>(S, xpt, tab, v);
       if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
       slotv[i] = r.slot;
       dv[i] = double(d);
@@ -355,13 +369,13 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 
 // LDS layout of a workgroup: [power table][G contribution regions][F partials]
 template <int L>
-__host__ __device__ inline size_t lds_bytes(int n, int tab_last, int max_slots, int R, int G) {
-  const size_t tab = tab_last >= 2 ? size_t(tab_last - 1) * n : 0;
+__host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int R, int G) {
+  const size_t tab = tab_last >= tab_first ? size_t(tab_last - tab_first + 1) * n : 0;
   return (tab + size_t(G) * max_slots + size_t(R)) * 2 * L * sizeof(double);
 }
 
 __device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
-  return S.tab_last >= 2 ? size_t(S.tab_last - 1) * S.n * 2 * L : 0;
+  return size_t(tab_entries(S)) * S.n * 2 * L;
 }
 
 // ------------------------------------------------------------------ kernels

@@ -41,7 +41,7 @@ pe_status fail(pe_status st, const std::string& msg) {
 
 // chunk slot budget per level: about 36 KB of LDS for D and DD (so that a
 // workgroup can hold four chunks at once), 68 KB for QD
-int default_seg(int L) { return L == 1 ? 8 : 4; }
+int default_seg(int L) { return L == 1 ? 8 : (L == 2 ? 8 : 4); }
 
 int default_slots(int L) { return L == 1 ? 2304 : (L == 2 ? 1152 : 1088); }
 
@@ -74,6 +74,7 @@ struct Plan {
   int seg = 4;
   int cpl = 1;
   int max_slots = 2048;
+  int tab_first = 2;
   int tab_last = 0;
   size_t lds = 0;   // this plan's workgroup LDS
   size_t lds1 = 0;  // LDS of a one-chunk workgroup (adjoint and batches)
@@ -238,15 +239,28 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 columns (n + R) is not supported");
   const size_t limit = device_lds_limit();
   const int L = H.level;
-  auto lds_for = [&](int tab_last, int G) { return lds_bytes<1>(H.n, tab_last, pl.max_slots, H.R, G) * L; };
-  pl.tab_last = 0;
-  if (H.emax - 1 >= 2 && lds_for(H.emax - 1, 1) <= limit) pl.tab_last = H.emax - 1;
+  auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, H.R, G) * L; };
+  // table of powers in LDS, in order of preference: for D and DD x itself
+  // first (its gathers are frequent next to cheap arithmetic) and then as
+  // many powers as fit; for QD only powers >= 2
+  std::vector<std::pair<int, int>> tables;
+  const int emax1 = std::max(H.emax - 1, 1);
+  if (L <= 2)
+    for (int tl = emax1; tl >= 1; --tl) tables.push_back({1, tl});
+  for (int tl = emax1; tl >= 2; --tl) tables.push_back({2, tl});
+  tables.push_back({2, 0});  // no table
+  auto pick_table = [&](int G) -> int {
+    for (size_t i = 0; i < tables.size(); ++i)
+      if (lds_for(tables[i].first, tables[i].second, G) <= limit) return int(i);
+    return -1;
+  };
   int max_chunks = 0;
   for (int p = 0; p < H.N; ++p) max_chunks = std::max<int>(max_chunks, H.chunk_ptr[p + 1] - H.chunk_ptr[p]);
   auto fits = [&](int G) {
     if (!shape_compiled(L, seg, G)) return false;
+    if (pick_table(G) < 0) return false;
     if (G == 1) return true;
-    return pl.cpl <= 2 && H.ncols * (G - 1) <= pl.max_slots * G && lds_for(pl.tab_last, G) <= limit;
+    return pl.cpl <= 2 && H.ncols * (G - 1) <= pl.max_slots * G;
   };
   if (force_G > 0) {
     if (!fits(force_G)) return fail(PE_EUNSUPPORTED, "this launch shape does not fit the system");
@@ -259,8 +273,12 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
         break;
       }
   }
-  pl.lds = lds_for(pl.tab_last, pl.G);
-  pl.lds1 = lds_for(pl.tab_last, 1);
+  const int ti = pick_table(pl.G);
+  if (ti < 0) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
+  pl.tab_first = tables[ti].first;
+  pl.tab_last = tables[ti].second;
+  pl.lds = lds_for(pl.tab_first, pl.tab_last, pl.G);
+  pl.lds1 = lds_for(pl.tab_first, pl.tab_last, 1);
   if (pl.lds > limit) return fail(PE_EUNSUPPORTED, "workgroup LDS need exceeds the device limit");
   sys->plan = pl;
   return PE_OK;
@@ -317,6 +335,7 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   V.R = P.R;
   V.ncols = P.ncols;
   V.emax = P.emax;
+  V.tab_first = sys->plan.tab_first;
   V.tab_last = sys->plan.tab_last;
   V.max_slots = sys->plan.max_slots;
   pe_status e = PE_OK;
@@ -485,6 +504,7 @@ pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_pe
       sys->plan = saved;
       return st;
     }
+    sys->view.tab_first = sys->plan.tab_first;
     sys->view.tab_last = sys->plan.tab_last;
     sys->view.max_slots = sys->plan.max_slots;
     return PE_OK;
