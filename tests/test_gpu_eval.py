@@ -180,10 +180,10 @@ def test_deterministic_and_shapes(pe):
     import torch
     sys_, x = synth.workload("dd_n256")
     S = pe.System.from_sparse(sys_)
-    assert S.info()["chunks_per_workgroup"] == 4
+    assert S.info()["chunks_per_workgroup"] > 1
     xd = U.to_device(x)
     outs = {}
-    for G in (4, 1):
+    for G in (S.info()["chunks_per_workgroup"], 1):
         S.set_shape(G)
         assert S.info()["chunks_per_workgroup"] == G
         a = [t.cpu().numpy() for t in S.eval(xd)]
@@ -193,7 +193,7 @@ def test_deterministic_and_shapes(pe):
         outs[G] = a
     tol = U.tolerance(sys_)
     rows = [0, 100, 255]
-    for G in (1, 4):
+    for G in outs:
         eF, eJ = U.max_errors_rows(sys_, x[0], outs[G][0][0], outs[G][1][0], rows, parallel=False)
         assert eF <= tol and eJ <= tol, (G, eF, eJ)
     S.close()
