@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/polyeval.h"
+#include "polyeval.h"
 #include "eval_kernels.hpp"
 #include "newton_kernels.hpp"
 #include "packer.hpp"
