@@ -200,20 +200,32 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
   const int base = k / s, extra = k - base * s;
   const int len = base + (q < extra ? 1 : 0);
 
+  // Issue every load of the lane before any arithmetic: the occurrence
+  // records (indices clamped inside the chunk, so lanes past their segment or
+  // past the chunk read valid padding records) and then the variables.
+  // Keeping the loads out of the per-variable branches lets their latencies
+  // overlap instead of adding up.
+  OccRec rec[SEG];
+  if (cd.width > 0) {
+    const int lane_c = min(lt, int(cd.width) - 1);
+    const int segc = cd.seg;
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) rec[i] = S.occ[cd.occ_base + size_t(min(i, segc - 1)) * cd.width + lane_c];
+  } else {
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) rec[i] = OccRec{0, 0, 0, 0};
+  }
   C<L> xv[SEG];
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) xv[i] = load_x<L>(S, xpt, tab, rec[i].var);
+
   C<L> pre[SEG > 1 ? SEG - 1 : 1];
-  int slotv[SEG];
-  double dv[SEG];
   C<L> A = c_one<L>();
 #pragma unroll
   for (int i = 0; i < SEG; ++i) {
     if (i < len) {
-      const OccRec r = S.occ[cd.occ_base + size_t(i) * cd.width + lt];
-      const int v = r.var, d = r.exp;
-      xv[i] = load_x<L>(S, xpt, tab, v);
+      const int v = rec[i].var, d = rec[i].exp;
       if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
-      slotv[i] = r.slot;
-      dv[i] = double(d);
       if (i == 0)
         A = xv[0];
       else
@@ -245,13 +257,13 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
     if (i < len) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      store_aos(contrib + size_t(slotv[i]) * (2 * L), c_mul_d(gi, dv[i]));
+      store_aos(contrib + size_t(rec[i].slot) * (2 * L), c_mul_d(gi, double(rec[i].exp)));
     }
   }
   if (len >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    store_aos(contrib + size_t(slotv[0]) * (2 * L), c_mul_d(g0, dv[0]));
+    store_aos(contrib + size_t(rec[0].slot) * (2 * L), c_mul_d(g0, double(rec[0].exp)));
   }
   if (MODE == MODE_EVAL && active && q == 0) store_aos(contrib + size_t(fslot) * (2 * L), Sx);
 }
@@ -262,7 +274,14 @@ __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&c
                                              C<L> (&acc)[CPL]) {
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    for (int sl = cb[cc]; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], load_aos<L>(contrib + size_t(sl) * (2 * L)));
+    // two slots per step: both loads are issued before the additions
+    int sl = cb[cc];
+    for (; sl + 1 < ce[cc]; sl += 2) {
+      const C<L> a = load_aos<L>(contrib + size_t(sl) * (2 * L));
+      const C<L> b = load_aos<L>(contrib + size_t(sl + 1) * (2 * L));
+      acc[cc] = c_add(c_add(acc[cc], a), b);
+    }
+    if (sl < ce[cc]) acc[cc] = c_add(acc[cc], load_aos<L>(contrib + size_t(sl) * (2 * L)));
   }
 }
 

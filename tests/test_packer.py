@@ -1,0 +1,118 @@
+"""Invariants of the host packer (owner-computes slot layout, lane-major
+records, chunk bounds), built with g++ from the library's sources."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1402_2626_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "paper_1402_2626_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("pack") / "libpack_host.so"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", os.path.join(HERE, "pack_host.cpp"),
+                    os.path.join(SRC, "packer.cpp"), "-o", str(out)], check=True)
+    lib = ctypes.CDLL(str(out))
+    lib.pe_test_pack_msg.restype = ctypes.c_char_p
+    return lib
+
+
+def pack(lib, s, seg, max_slots=1152):
+    arrs = [np.ascontiguousarray(a) for a in (s.poly_ptr, s.mon_ptr, s.var_idx, s.exps, s.coef)]
+    sizes = np.zeros(8, np.int64)
+    st = lib.pe_test_pack(s.level, s.n_vars, s.n_polys, *[ctypes.c_void_p(a.ctypes.data) for a in arrs],
+                          seg, max_slots, ctypes.c_void_p(sizes.ctypes.data))
+    assert st == 0, lib.pe_test_pack_msg()
+    nch, nocc, ncol, M = int(sizes[0]), int(sizes[1]), int(sizes[2]), int(sizes[3])
+    chunks = np.zeros((nch, 9), np.int64)
+    occ = np.zeros((nocc, 4), np.uint16)
+    colptr = np.zeros(ncol, np.uint16)
+    mmeta = np.zeros(M, np.uint32)
+    mcoef = np.zeros(M * 2 * s.level)
+    cptr = np.zeros(s.n_polys + 1, np.uint32)
+    lib.pe_test_pack_get(*[ctypes.c_void_p(a.ctypes.data) for a in (chunks, occ, colptr, mmeta, mcoef, cptr)])
+    return dict(chunks=chunks, occ=occ, colptr=colptr, mmeta=mmeta, mcoef=mcoef, chunk_ptr=cptr, R=int(sizes[4]),
+                ncols=int(sizes[5]), max_slots_used=int(sizes[6]))
+
+
+def lanes_for(k, seg):
+    need = (k + seg - 1) // seg
+    s = 1
+    while s < need:
+        s <<= 1
+    return s
+
+
+@pytest.mark.parametrize("seg", [2, 4, 8])
+def test_pack_invariants(lib, seg):
+    s = synth.random_system(7, 2, n_vars=60, n_polys=9, m=70, k=11, exp_lo=1, exp_hi=4)
+    # mixed sizes: add monomials of other lengths to one polynomial
+    polys = []
+    for p in range(s.n_polys):
+        mons = []
+        for t in range(int(s.poly_ptr[p]), int(s.poly_ptr[p + 1])):
+            vs, ds = s.monomial(t)
+            mons.append((0, list(zip(vs.tolist(), ds.tolist()))))
+        polys.append(mons)
+    rng = synth.rng_for(8)
+    for k in (0, 1, 3, 31, 40):
+        vs = np.sort(rng.choice(60, size=k, replace=False))
+        polys[2].append((0, [(int(v), 2) for v in vs]))
+    polys.append([])  # empty polynomial
+    coef = synth.unit_circle(rng, sum(len(m) for m in polys), 2)
+    s = synth.from_monomial_lists(2, 60, polys, coef_limbs=coef)
+    P = pack(lib, s, seg)
+    ncols, R = P["ncols"], P["R"]
+    assert ncols == 60 + R
+    seen_mon = set()
+    for p in range(s.n_polys):
+        # monomials of polynomial p, as multisets of (var, exp)
+        want = sorted(tuple(sorted(zip(*[a.tolist() for a in s.monomial(t)])))
+                      for t in range(int(s.poly_ptr[p]), int(s.poly_ptr[p + 1])))
+        got = []
+        for ch in range(int(P["chunk_ptr"][p]), int(P["chunk_ptr"][p + 1])):
+            ob, mb, cb, poly, count, nslots, width, sl, segc = P["chunks"][ch]
+            assert poly == p and width == count * sl and sl <= 64 and segc <= seg
+            cp = P["colptr"][cb:cb + ncols + 1].astype(int)
+            assert cp[0] == 0 and cp[-1] == nslots and np.all(np.diff(cp) >= 0)
+            col_of_slot = np.repeat(np.arange(ncols), np.diff(cp))
+            slots = []
+            for g in range(count):
+                meta = int(P["mmeta"][mb + g])
+                k, fslot = meta & 0xFFFF, meta >> 16
+                assert lanes_for(max(k, 1), seg) <= sl
+                assert col_of_slot[fslot] == 60 + g % R
+                slots.append(fslot)
+                occs = []
+                base, extra = k // sl, k % sl
+                for q in range(sl):
+                    ln = base + (1 if q < extra else 0)
+                    for i in range(ln):
+                        var, ex, slot, _ = P["occ"][ob + i * width + g * sl + q]
+                        occs.append((int(var), int(ex)))
+                        assert col_of_slot[slot] == var
+                        slots.append(int(slot))
+                assert [v for v, _ in occs] == sorted(v for v, _ in occs)  # canonical order
+                got.append(tuple(occs))
+                seen_mon.add(mb + g)
+            assert sorted(slots) == list(range(nslots)), "slots must be a permutation"
+            # within a column, slots follow (monomial, position) order
+            for c in range(ncols):
+                seg_slots = list(range(cp[c], cp[c + 1]))
+                assert seg_slots == sorted(seg_slots)
+        assert sorted(got) == want
+    assert len(seen_mon) == s.n_monomials
+
+
+def test_chunk_budget(lib):
+    s = synth.random_system(9, 4, n_vars=300, n_polys=2, m=500, k=20, exp_lo=1, exp_hi=2)
+    P = pack(lib, s, 4, max_slots=1100)
+    assert P["max_slots_used"] <= 1100
+    assert np.all(P["chunks"][:, 5] <= 1100)
+    assert np.all(P["chunks"][:, 6] <= 256)
