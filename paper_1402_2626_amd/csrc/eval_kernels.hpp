@@ -38,7 +38,7 @@ namespace pe {
 enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2 };
 
 struct SysView {
-  int n, N, R, ncols;
+  int n, N, R, fcol, ncols;  // F partial columns fcol .. fcol+R-1 (layout.hpp)
   int emax;
   int tab_first;  // powers tab_first..tab_last of every variable are in the
   int tab_last;   // LDS table (tab_first = 1: x itself too; none if last < first)
@@ -131,20 +131,32 @@ __device__ __forceinline__ int tab_entries(const SysView& S) {
   return S.tab_last >= S.tab_first ? S.tab_last - S.tab_first + 1 : 0;
 }
 
+// LDS arrays of complex multi-doubles are planar (component k of element i at
+// base[k * stride + i], components re limbs then im limbs): a wavefront's
+// gather then reads 8-byte words spread over all banks, where 32-byte records
+// would map every lane's access onto the same half of the banks.
+
+// powers x_v^e, e = tab_first..tab_last: table block e - tab_first holds
+// 2L planes of n doubles
+template <int L>
+__device__ __forceinline__ const double* tab_block(const SysView& S, const double* tab, int e) {
+  return tab + size_t(e - S.tab_first) * (2 * L) * S.n;
+}
+
 // x^e (e >= 2) from the LDS table, from the table's highest power times x,
 // or by binary powering
 template <int L>
 __device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, int v, int e, const C<L>& xv) {
-  if (e >= S.tab_first && e <= S.tab_last) return load_aos<L>(tab + (size_t(e - S.tab_first) * S.n + v) * (2 * L));
+  if (e >= S.tab_first && e <= S.tab_last) return load_planar<L>(tab_block<L>(S, tab, e), S.n, v);
   if (e == S.tab_last + 1 && S.tab_last >= S.tab_first && S.tab_last >= 2)
-    return c_mul(load_aos<L>(tab + (size_t(S.tab_last - S.tab_first) * S.n + v) * (2 * L)), xv);
+    return c_mul(load_planar<L>(tab_block<L>(S, tab, S.tab_last), S.n, v), xv);
   return c_pow(xv, e);
 }
 
 // x_v for a gathered variable: from the LDS table when it holds x
 template <int L>
 __device__ __forceinline__ C<L> load_x(const SysView& S, const double* __restrict__ xpt, const double* tab, int v) {
-  if (S.tab_first == 1 && S.tab_last >= 1) return load_aos<L>(tab + size_t(v) * (2 * L));
+  if (S.tab_first == 1 && S.tab_last >= 1) return load_planar<L>(tab, S.n, v);
   return load_planar<L>(xpt, S.n, v);
 }
 
@@ -157,7 +169,7 @@ __device__ void build_power_table(const SysView& S, const double* __restrict__ x
     C<L> p = x1;
     for (int e = 1; e <= S.tab_last; ++e) {
       if (e > 1) p = c_mul(p, x1);
-      if (e >= S.tab_first) store_aos(tab + (size_t(e - S.tab_first) * S.n + v) * (2 * L), p);
+      if (e >= S.tab_first) store_planar(const_cast<double*>(tab_block<L>(S, tab, e)), S.n, v, p);
     }
   }
 }
@@ -172,59 +184,95 @@ __device__ void build_power_table(const SysView& S, const double* __restrict__ x
 
 constexpr int kSub = 256;
 
-// Monomial phase of one chunk: writes every contribution of the chunk into
-// its LDS slot.  All lanes of the sub-group call it (the butterfly needs the
-// whole wavefront).  In MODE_ADJ the coefficient of a monomial of polynomial
-// p is multiplied by conj(v_p).
-template <int L, int SEG, int MODE>
-__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDesc& cd, int lt,
-                                                const double* __restrict__ xpt,
-                                                const double* __restrict__ vpt, const double* tab,
-                                                double* contrib) {
+// sub-group of the calling thread, as a wavefront-uniform value (kSub is a
+// multiple of the wavefront size)
+__device__ __forceinline__ int sub_group() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kSub); }
+
+// Everything a lane reads from global memory for one chunk.  The loads are
+// issued well before their first use (before the power table is built, or
+// while the previous chunk's owners add), so their latencies overlap.
+template <int L, int SEG, int CPL>
+struct ChunkLoads {
+  ChunkDesc cd;      // wavefront-uniform
+  OccRec rec[SEG];   // the lane's segment (indices clamped into the chunk)
+  uint32_t meta;     // k | F slot << 16 of the lane's monomial
+  C<L> coef;         // coefficient on lane 0 of a monomial's group, else 1
+  C<L> vp;           // adjoint weight v_p of the chunk's polynomial
+  int cb[CPL], ce[CPL];  // slot ranges of the lane's owned columns
+};
+
+template <int L, int SEG, int CPL, int MODE>
+__device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool act, int lt,
+                                           const double* __restrict__ vpt, ChunkLoads<L, SEG, CPL>& cl) {
+  const uint32_t chu = uint32_t(__builtin_amdgcn_readfirstlane(int(ch)));
+  if (act) {
+    cl.cd = S.chunks[chu];
+  } else {
+    cl.cd = ChunkDesc{};
+    cl.cd.s = 1;
+  }
+  const ChunkDesc& cd = cl.cd;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int c = lt + cc * kSub;
+    bool use = act && c < S.ncols;
+    if (MODE == MODE_FONLY) use = use && c >= S.fcol;
+    if (MODE == MODE_ADJ) use = use && c < S.n;
+    cl.cb[cc] = use ? int(S.colptr[cd.colptr_base + c]) : 0;
+    cl.ce[cc] = use ? int(S.colptr[cd.colptr_base + c + 1]) : 0;
+  }
   const int s = cd.s;
   const int g = lt / s;
   const int q = lt & (s - 1);
   const bool active = g < int(cd.count);
-
-  int k = 0, fslot = 0;
-  C<L> cf = c_one<L>();
-  if (active) {
-    const uint32_t meta = S.mmeta[cd.mon_base + g];
-    k = int(meta & 0xffffu);
-    fslot = int(meta >> 16);
-    if (q == 0) {
-      cf = load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * (2 * L));
-      if (MODE == MODE_ADJ) cf = c_mul(cf, c_conj(load_planar<L>(vpt, S.N, cd.poly)));
-    }
-  }
-  const int base = k / s, extra = k - base * s;
-  const int len = base + (q < extra ? 1 : 0);
-
-  // Issue every load of the lane before any arithmetic: the occurrence
-  // records (indices clamped inside the chunk, so lanes past their segment or
-  // past the chunk read valid padding records) and then the variables.
-  // Keeping the loads out of the per-variable branches lets their latencies
-  // overlap instead of adding up.
-  OccRec rec[SEG];
+  cl.meta = active ? S.mmeta[cd.mon_base + g] : 0u;
+  cl.coef = (active && q == 0) ? load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * (2 * L)) : c_one<L>();
+  if (MODE == MODE_ADJ) cl.vp = act ? load_planar<L>(vpt, S.N, cd.poly) : c_zero<L>();
+  // records of lanes past their segment or past the chunk are valid padding
   if (cd.width > 0) {
     const int lane_c = min(lt, int(cd.width) - 1);
     const int segc = cd.seg;
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) rec[i] = S.occ[cd.occ_base + size_t(min(i, segc - 1)) * cd.width + lane_c];
+    for (int i = 0; i < SEG; ++i) cl.rec[i] = S.occ[cd.occ_base + size_t(min(i, segc - 1)) * cd.width + lane_c];
   } else {
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) rec[i] = OccRec{0, 0, 0, 0};
+    for (int i = 0; i < SEG; ++i) cl.rec[i] = OccRec{0, 0, 0, 0};
   }
+}
+
+// Monomial phase of one chunk: writes every contribution of the chunk into
+// its LDS slot (planar, plane stride max_slots).  All lanes of the sub-group
+// call it (the butterfly needs the whole wavefront).  In MODE_ADJ the
+// coefficient of a monomial of polynomial p is multiplied by conj(v_p).
+template <int L, int SEG, int CPL, int MODE>
+__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
+                                                const double* __restrict__ xpt, const double* tab,
+                                                double* contrib) {
+  const ChunkDesc& cd = cl.cd;
+  const int s = cd.s;
+  const int g = lt / s;
+  const int q = lt & (s - 1);
+  const bool active = g < int(cd.count);
+  const int k = int(cl.meta & 0xffffu);
+  const int fslot = int(cl.meta >> 16);
+  C<L> cf = cl.coef;
+  if (MODE == MODE_ADJ && active && q == 0) cf = c_mul(cf, c_conj(cl.vp));
+  const int base = k / s, extra = k - base * s;
+  const int len = base + (q < extra ? 1 : 0);
+  const int ms = S.max_slots;
+
+  // every gather of the segment before any arithmetic, so that the LDS
+  // latencies overlap
   C<L> xv[SEG];
 #pragma unroll
-  for (int i = 0; i < SEG; ++i) xv[i] = load_x<L>(S, xpt, tab, rec[i].var);
+  for (int i = 0; i < SEG; ++i) xv[i] = load_x<L>(S, xpt, tab, cl.rec[i].var);
 
   C<L> pre[SEG > 1 ? SEG - 1 : 1];
   C<L> A = c_one<L>();
 #pragma unroll
   for (int i = 0; i < SEG; ++i) {
     if (i < len) {
-      const int v = rec[i].var, d = rec[i].exp;
+      const int v = cl.rec[i].var, d = cl.rec[i].exp;
       if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
       if (i == 0)
         A = xv[0];
@@ -247,7 +295,7 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
   }
   if (MODE == MODE_FONLY) {
     // B is now the monomial's value on every lane of the group
-    if (active && q == 0) store_aos(contrib + size_t(fslot) * (2 * L), B);
+    if (active && q == 0) store_planar(contrib, ms, fslot, B);
     return;
   }
   // reverse sweep of Speelpenning's product over the segment
@@ -257,96 +305,80 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkDes
     if (i < len) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      store_aos(contrib + size_t(rec[i].slot) * (2 * L), c_mul_d(gi, double(rec[i].exp)));
+      store_planar(contrib, ms, cl.rec[i].slot, c_mul_d(gi, double(cl.rec[i].exp)));
     }
   }
   if (len >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    store_aos(contrib + size_t(rec[0].slot) * (2 * L), c_mul_d(g0, double(rec[0].exp)));
+    store_planar(contrib, ms, cl.rec[0].slot, c_mul_d(g0, double(cl.rec[0].exp)));
   }
-  if (MODE == MODE_EVAL && active && q == 0) store_aos(contrib + size_t(fslot) * (2 * L), Sx);
+  if (MODE == MODE_EVAL && active && q == 0) store_planar(contrib, ms, fslot, Sx);
 }
 
-// Owner phase: add the chunk's slots into the register accumulators.
+// Owner phase: add the chunk's slots into the register accumulators, four
+// slots per step as acc + ((a + b) + (c + d)) (the tail one by one), so that
+// the loads of a step are in flight together and the additions form short
+// chains.  The order depends only on the slot layout.
 template <int L, int CPL>
 __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&ce)[CPL], const double* contrib,
-                                             C<L> (&acc)[CPL]) {
+                                             int ms, C<L> (&acc)[CPL]) {
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    // two slots per step: both loads are issued before the additions
     int sl = cb[cc];
-    for (; sl + 1 < ce[cc]; sl += 2) {
-      const C<L> a = load_aos<L>(contrib + size_t(sl) * (2 * L));
-      const C<L> b = load_aos<L>(contrib + size_t(sl + 1) * (2 * L));
-      acc[cc] = c_add(c_add(acc[cc], a), b);
+    for (; sl + 3 < ce[cc]; sl += 4) {
+      const C<L> a = load_planar<L>(contrib, ms, sl);
+      const C<L> b = load_planar<L>(contrib, ms, sl + 1);
+      const C<L> c = load_planar<L>(contrib, ms, sl + 2);
+      const C<L> d = load_planar<L>(contrib, ms, sl + 3);
+      acc[cc] = c_add(acc[cc], c_add(c_add(a, b), c_add(c, d)));
     }
-    if (sl < ce[cc]) acc[cc] = c_add(acc[cc], load_aos<L>(contrib + size_t(sl) * (2 * L)));
-  }
-}
-
-// Columns of the accumulator slot cc of local thread lt: lt + cc * kSub.
-template <int CPL, int MODE>
-__device__ __forceinline__ void chunk_colptr(const SysView& S, const ChunkDesc& cd, bool act, int lt,
-                                             int (&cb)[CPL], int (&ce)[CPL]) {
-#pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) {
-    const int c = lt + cc * kSub;
-    bool use = act && c < S.ncols;
-    if (MODE == MODE_FONLY) use = use && c >= S.n;
-    if (MODE == MODE_ADJ) use = use && c < S.n;
-    if (use) {
-      cb[cc] = S.colptr[cd.colptr_base + c];
-      ce[cc] = S.colptr[cd.colptr_base + c + 1];
-    } else {
-      cb[cc] = 0;
-      ce[cc] = 0;
-    }
+    for (; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], load_planar<L>(contrib, ms, sl));
   }
 }
 
 // Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
-// ch0 + sg, ch0 + sg + G, ...
+// ch0 + sg, ch0 + sg + G, ...  `cl` holds the loads of the sub-group's first
+// chunk, issued by the caller; the loads of each next chunk are issued before
+// the owner phase of the current one.
 template <int L, int SEG, int CPL, int G, int MODE>
-__device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1, const double* __restrict__ xpt,
-                               const double* __restrict__ vpt, const double* tab, double* contrib_base,
-                               C<L> (&acc)[CPL]) {
-  const int sg = threadIdx.x / kSub;
-  const int lt = threadIdx.x - sg * kSub;
+__device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1,
+                                               const double* __restrict__ xpt, const double* __restrict__ vpt,
+                                               const double* tab, double* contrib_base, C<L> (&acc)[CPL],
+                                               ChunkLoads<L, SEG, CPL>& cl) {
+  const int sg = sub_group();
+  const int lt = int(threadIdx.x) - sg * kSub;
   double* contrib = contrib_base + size_t(sg) * S.max_slots * 2 * L;
   for (uint32_t base = ch0; base < ch1; base += G) {
-    const uint32_t ch = base + sg;
-    const bool act = ch < ch1;
-    ChunkDesc cd;
-    if (act) {
-      cd = S.chunks[ch];
-    } else {
-      cd = ChunkDesc{};
-      cd.s = 1;
-    }
-    int cb[CPL], ce[CPL];
-    chunk_colptr<CPL, MODE>(S, cd, act, lt, cb, ce);
-    chunk_monomials<L, SEG, MODE>(S, cd, lt, xpt, vpt, tab, contrib);
+    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib);
     __syncthreads();
-    chunk_owners<L, CPL>(cb, ce, contrib, acc);
+    int cb[CPL], ce[CPL];
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      cb[cc] = cl.cb[cc];
+      ce[cc] = cl.ce[cc];
+    }
+    if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    chunk_owners<L, CPL>(cb, ce, contrib, S.max_slots, acc);
     __syncthreads();
   }
 }
 
 // Write row p of J and F from the accumulators (EVAL / FONLY).  With G > 1
 // sub-groups 1..G-1 first hand their partial rows to sub-group 0 through
-// LDS (the contribution region is free by then), which adds them in order.
+// LDS (the contribution regions are free by then), which adds them in order.
+// No LDS is in use when it returns.
 template <int L, int CPL, int G, int MODE>
-__device__ __forceinline__ void write_row(const SysView& S, const OutView& O, int pt, int p, C<L> (&acc)[CPL], double* scratch,
-                          double* fpart) {
-  const int sg = threadIdx.x / kSub;
-  const int lt = threadIdx.x - sg * kSub;
+__device__ __forceinline__ void write_row(const SysView& S, const OutView& O, int pt, int p, C<L> (&acc)[CPL],
+                                          double* scratch) {
+  const int sg = sub_group();
+  const int lt = int(threadIdx.x) - sg * kSub;
   if (G > 1) {
     if (sg > 0) {
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         const int c = lt + cc * kSub;
-        if (c < S.ncols) store_aos(scratch + (size_t(sg - 1) * S.ncols + c) * (2 * L), acc[cc]);
+        if (c < S.ncols) store_planar(scratch + size_t(sg - 1) * (2 * L) * S.ncols, S.ncols, c, acc[cc]);
       }
     }
     __syncthreads();
@@ -355,42 +387,52 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           const int c = lt + cc * kSub;
-          if (c < S.ncols) acc[cc] = c_add(acc[cc], load_aos<L>(scratch + (size_t(o - 1) * S.ncols + c) * (2 * L)));
+          if (c < S.ncols)
+            acc[cc] = c_add(acc[cc], load_planar<L>(scratch + size_t(o - 1) * (2 * L) * S.ncols, S.ncols, c));
         }
       }
     }
   }
-  if (sg == 0) {
+  if (sg != 0) return;
+  if (MODE == MODE_EVAL) {
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
-      if (c < S.n) {
-        if (MODE == MODE_EVAL) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
-      } else if (c < S.ncols) {
-        store_aos(fpart + size_t(c - S.n) * (2 * L), acc[cc]);
-      }
+      if (c < S.n) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
     }
   }
-  __syncthreads();
-  // F = sum of the R partial columns, added pairwise across the lanes of the
-  // first wavefront (R <= 32)
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
-    C<L> f = r < S.R ? load_aos<L>(fpart + size_t(r) * (2 * L)) : c_zero<L>();
+  // F = sum of the R partial columns.  They lie in one aligned block of 64
+  // columns, so one wavefront of sub-group 0 holds them all: partial r is
+  // rotated to lane r, and lanes 0..31 are added pairwise.
+  const int fcc = S.fcol / kSub;
+  if (lt / 64 == (S.fcol % kSub) / 64) {
+    const int lane = lt & 63;
+    const int off = S.fcol & 63;
+    C<L> v = c_zero<L>();
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc)
+      if (cc == fcc) v = acc[cc];
+    if (lane < off || lane >= off + S.R) v = c_zero<L>();
+    C<L> f;
+    const int src = (lane + off) & 63;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      f.re.x[l] = __shfl(v.re.x[l], src);
+      f.im.x[l] = __shfl(v.im.x[l], src);
+    }
     for (int m = 1; m < 32; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
-    if (r == 0) {
+    if (lane == 0) {
       if (O.f_sign < 0) f = c_neg(f);
       store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, f);
     }
   }
-  __syncthreads();
 }
 
-// LDS layout of a workgroup: [power table][G contribution regions][F partials]
+// LDS layout of a workgroup: [power table][G contribution regions]
 template <int L>
-__host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int R, int G) {
+__host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int G) {
   const size_t tab = tab_last >= tab_first ? size_t(tab_last - tab_first + 1) * n : 0;
-  return (tab + size_t(G) * max_slots + size_t(R)) * 2 * L * sizeof(double);
+  return (tab + size_t(G) * max_slots) * 2 * L * sizeof(double);
 }
 
 __device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
@@ -410,14 +452,17 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   const double* xpt = x + pt * x_pt;
   double* tab = lds;
   double* contrib = lds + tab_doubles(S, L);
-  double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
+  const int sg = sub_group();
+  const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
+  ChunkLoads<L, SEG, CPL> cl;
+  load_chunk<L, SEG, CPL, MODE>(S, ch0 + sg, ch0 + sg < ch1, int(threadIdx.x) - sg * kSub, nullptr, cl);
   build_power_table<L, G * kSub>(S, xpt, tab);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, G, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
-  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+  process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, cl);
+  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib);
 }
 
 // Adjoint: grid P * NG workgroups of 256 threads; group gi covers
@@ -434,14 +479,17 @@ __global__ __launch_bounds__(kSub) void adjoint_rows_kernel(SysView S, const dou
   const double* vpt = v + pt * v_pt;
   double* tab = lds;
   double* contrib = lds + tab_doubles(S, L);
+  const int p0 = gi * gsize;
+  const int p1 = min(S.N, p0 + gsize);
+  const uint32_t ch0 = S.chunk_ptr[p0], ch1 = S.chunk_ptr[p1];
+  ChunkLoads<L, SEG, CPL> cl;
+  load_chunk<L, SEG, CPL, MODE_ADJ>(S, ch0, ch0 < ch1, int(threadIdx.x), vpt, cl);
   build_power_table<L, kSub>(S, xpt, tab);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  const int p0 = gi * gsize;
-  const int p1 = min(S.N, p0 + gsize);
-  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, S.chunk_ptr[p0], S.chunk_ptr[p1], xpt, vpt, tab, contrib, acc);
+  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, ch0, ch1, xpt, vpt, tab, contrib, acc, cl);
   double* out = part + size_t(pt * NG + gi) * 2 * L * S.n;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
@@ -526,16 +574,18 @@ __global__ __launch_bounds__(kSub) void batch_rows_kernel(const SysView* __restr
     }
     double* tab = lds;
     double* contrib = lds + tab_doubles(S, L);
-    double* fpart = contrib + size_t(S.max_slots) * 2 * L;
+    const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
     for (int pt = 0; pt < P; ++pt) {
       const double* xpt = x + x_off[s] * P + int64_t(pt) * 2 * L * n;
+      ChunkLoads<L, SEG, CPL> cl;
+      load_chunk<L, SEG, CPL, MODE>(S, ch0, ch0 < ch1, int(threadIdx.x), nullptr, cl);
       build_power_table<L, kSub>(S, xpt, tab);
       __syncthreads();
       C<L> acc[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-      process_chunks<L, SEG, CPL, 1, MODE>(S, S.chunk_ptr[p], S.chunk_ptr[p + 1], xpt, nullptr, tab, contrib, acc);
-      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib, fpart);
+      process_chunks<L, SEG, CPL, 1, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, cl);
+      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib);
     }
   }
 }

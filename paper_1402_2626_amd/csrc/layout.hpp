@@ -8,10 +8,12 @@
 // variables, and each partial derivative (and the monomial's value) is written
 // to its own LDS SLOT.  Slots are numbered so that the contributions to one
 // output column are contiguous: column c owns slots colptr[c] ..
-// colptr[c+1]-1.  Columns 0..n-1 are the Jacobian columns; columns n..n+R-1
+// colptr[c+1]-1.  Columns 0..n-1 are the Jacobian columns; columns
+// fcol..fcol+R-1 (fcol >= n, the block inside one aligned run of 64 columns)
 // are R partial sums of F (monomial g of a chunk adds its value to column
-// n + g % R), summed in order at the end.  This owner-computes order is fixed
-// at load time, so results are bitwise reproducible.
+// fcol + g % R), summed in order at the end; columns between n and fcol stay
+// empty.  This owner-computes order is fixed at load time, so results are
+// bitwise reproducible.
 #pragma once
 #include <cstdint>
 

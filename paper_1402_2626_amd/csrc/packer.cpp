@@ -149,7 +149,10 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
     R = std::max(1, std::min(R, 32));
   }
   out.R = R;
-  out.ncols = n + R;
+  // the R partial columns lie inside one aligned block of 64 columns, so
+  // that one wavefront holds all of them when F is summed
+  out.fcol = (n % kMaxWave) + R <= kMaxWave ? n : (n + kMaxWave - 1) / kMaxWave * kMaxWave;
+  out.ncols = out.fcol + R;
   if (out.ncols + 1 > 65535) {
     msg = "too many columns";
     return kEunsupported;
@@ -226,7 +229,7 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
         for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o]});
         std::sort(occ_sorted.begin(), occ_sorted.end(), [](const Occ& x, const Occ& y) { return x.var < y.var; });
         for (int r = 0; r < int(occ_sorted.size()); ++r) contribs.push_back({occ_sorted[r].var, g, r, 0});
-        contribs.push_back({n + g % R, g, 1 << 20, 0});
+        contribs.push_back({out.fcol + g % R, g, 1 << 20, 0});
       }
       std::vector<Contrib> sorted = contribs;
       std::stable_sort(sorted.begin(), sorted.end(), [](const Contrib& x, const Contrib& y) {

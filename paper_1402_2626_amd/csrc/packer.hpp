@@ -33,7 +33,7 @@ struct Packed {
   int level = 0, n = 0, N = 0;
   int64_t M = 0, nnz = 0;
   int emax = 1, kmax = 0;
-  int R = 1, ncols = 1;
+  int R = 1, fcol = 1, ncols = 1;  // F partial columns fcol .. fcol+R-1
   PackParams params;
   int max_slots_used = 0;
   int max_seg_used = 1;

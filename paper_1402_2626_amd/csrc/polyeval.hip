@@ -239,7 +239,7 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 columns (n + R) is not supported");
   const size_t limit = device_lds_limit();
   const int L = H.level;
-  auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, H.R, G) * L; };
+  auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, G) * L; };
   // table of powers in LDS, in order of preference: for D and DD x itself
   // first (its gathers are frequent next to cheap arithmetic) and then as
   // many powers as fit; for QD only powers >= 2
@@ -333,6 +333,7 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   V.n = P.n;
   V.N = P.N;
   V.R = P.R;
+  V.fcol = P.fcol;
   V.ncols = P.ncols;
   V.emax = P.emax;
   V.tab_first = sys->plan.tab_first;

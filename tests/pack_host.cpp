@@ -12,7 +12,7 @@ static std::string g_msg;
 
 extern "C" int pe_test_pack(int level, int n, int N, const int64_t* poly_ptr, const int64_t* mon_ptr,
                             const int32_t* var_idx, const int32_t* exps, const double* coef, int seg, int max_slots,
-                            int64_t* sizes /* [8] */) {
+                            int64_t* sizes /* [9] */) {
   SysInput in;
   in.level = level;
   in.n_vars = n;
@@ -36,6 +36,7 @@ extern "C" int pe_test_pack(int level, int n, int N, const int64_t* poly_ptr, co
   sizes[5] = g_packed.ncols;
   sizes[6] = g_packed.max_slots_used;
   sizes[7] = g_packed.emax;
+  sizes[8] = g_packed.fcol;
   return 0;
 }
 

@@ -25,7 +25,7 @@ def lib(tmp_path_factory):
 
 def pack(lib, s, seg, max_slots=1152):
     arrs = [np.ascontiguousarray(a) for a in (s.poly_ptr, s.mon_ptr, s.var_idx, s.exps, s.coef)]
-    sizes = np.zeros(8, np.int64)
+    sizes = np.zeros(9, np.int64)
     st = lib.pe_test_pack(s.level, s.n_vars, s.n_polys, *[ctypes.c_void_p(a.ctypes.data) for a in arrs],
                           seg, max_slots, ctypes.c_void_p(sizes.ctypes.data))
     assert st == 0, lib.pe_test_pack_msg()
@@ -38,7 +38,7 @@ def pack(lib, s, seg, max_slots=1152):
     cptr = np.zeros(s.n_polys + 1, np.uint32)
     lib.pe_test_pack_get(*[ctypes.c_void_p(a.ctypes.data) for a in (chunks, occ, colptr, mmeta, mcoef, cptr)])
     return dict(chunks=chunks, occ=occ, colptr=colptr, mmeta=mmeta, mcoef=mcoef, chunk_ptr=cptr, R=int(sizes[4]),
-                ncols=int(sizes[5]), max_slots_used=int(sizes[6]))
+                ncols=int(sizes[5]), max_slots_used=int(sizes[6]), fcol=int(sizes[8]))
 
 
 def lanes_for(k, seg):
@@ -68,8 +68,10 @@ def test_pack_invariants(lib, seg):
     coef = synth.unit_circle(rng, sum(len(m) for m in polys), 2)
     s = synth.from_monomial_lists(2, 60, polys, coef_limbs=coef)
     P = pack(lib, s, seg)
-    ncols, R = P["ncols"], P["R"]
-    assert ncols == 60 + R
+    ncols, R, fcol = P["ncols"], P["R"], P["fcol"]
+    # the F partial columns sit in one aligned block of 64 columns
+    assert fcol >= 60 and ncols == fcol + R and fcol // 64 == (fcol + R - 1) // 64
+    assert fcol == (60 if 60 % 64 + R <= 64 else 64)
     seen_mon = set()
     for p in range(s.n_polys):
         # monomials of polynomial p, as multisets of (var, exp)
@@ -82,12 +84,13 @@ def test_pack_invariants(lib, seg):
             cp = P["colptr"][cb:cb + ncols + 1].astype(int)
             assert cp[0] == 0 and cp[-1] == nslots and np.all(np.diff(cp) >= 0)
             col_of_slot = np.repeat(np.arange(ncols), np.diff(cp))
+            assert np.all(np.diff(cp)[60:fcol] == 0)  # no slots between the J and F columns
             slots = []
             for g in range(count):
                 meta = int(P["mmeta"][mb + g])
                 k, fslot = meta & 0xFFFF, meta >> 16
                 assert lanes_for(max(k, 1), seg) <= sl
-                assert col_of_slot[fslot] == 60 + g % R
+                assert col_of_slot[fslot] == fcol + g % R
                 slots.append(fslot)
                 occs = []
                 base, extra = k // sl, k % sl
