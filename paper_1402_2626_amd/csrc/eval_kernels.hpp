@@ -17,16 +17,19 @@
 //      factor x other segments, so each partial derivative comes out already
 //      multiplied by the common factor and the coefficient; it is then
 //      multiplied by its exponent (Sec. 2.3) and written to its LDS slot; the
-//      monomial's value is what the sweep leaves at the end;
+//      monomial's value is what the sweep leaves at the end, and lane 0 of
+//      the group adds it to its running sum of F terms (a register);
 //   4. after a barrier the owner lanes add the slots of their columns in a
 //      fixed order (the sum reduction of Sec. 2.3), keeping row accumulators
 //      in registers across chunks.
-// At the end the row of J is written with coalesced stores and F is the
-// ordered sum of the R partial columns.
+// At the end the row of J is written with coalesced stores, and F is the sum
+// of the lanes' running sums, pairwise within each wavefront and then over
+// the wavefronts in order.
 //
-// The table of pure powers x_j^e (Sec. 2.1) for e = 2 .. emax-1 is built in
-// LDS by every workgroup when it fits; otherwise powers are formed by binary
-// powering from x.
+// The table of pure powers x_j^e (Sec. 2.1) is built in LDS by every
+// workgroup when it fits; otherwise powers are formed by binary powering from
+// x.  It has one extra column, variable n, holding the constant 1: the
+// neutral records that pad short segments point there.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -38,16 +41,16 @@ namespace pe {
 enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2 };
 
 struct SysView {
-  int n, N, R, fcol, ncols;  // F partial columns fcol .. fcol+R-1 (layout.hpp)
+  int n, N;
   int emax;
   int tab_first;  // powers tab_first..tab_last of every variable are in the
   int tab_last;   // LDS table (tab_first = 1: x itself too; none if last < first)
-  int max_slots;
+  int max_slots;  // slots of a contribution region (largest nslots + 1)
   const ChunkDesc* chunks;
   const uint32_t* chunk_ptr;
+  const ChunkDesc* rowdesc;  // [N][kRowDesc], see layout.hpp
   const OccRec* occ;
   const double* mcoef;  // [M][2L]
-  const uint32_t* mmeta;
   const uint16_t* colptr;
 };
 
@@ -136,40 +139,58 @@ __device__ __forceinline__ int tab_entries(const SysView& S) {
 // gather then reads 8-byte words spread over all banks, where 32-byte records
 // would map every lane's access onto the same half of the banks.
 
+// the power table has n + 1 columns: the variables and the constant 1
+__device__ __forceinline__ int tab_cols(const SysView& S) { return S.n + 1; }
+
 // powers x_v^e, e = tab_first..tab_last: table block e - tab_first holds
-// 2L planes of n doubles
+// 2L planes of n + 1 doubles
 template <int L>
 __device__ __forceinline__ const double* tab_block(const SysView& S, const double* tab, int e) {
-  return tab + size_t(e - S.tab_first) * (2 * L) * S.n;
+  return tab + size_t(e - S.tab_first) * (2 * L) * tab_cols(S);
+}
+
+// the table holds x itself and every power a common factor needs
+__device__ __forceinline__ bool tab_full(const SysView& S) {
+  return S.tab_first == 1 && S.tab_last >= S.emax - 1;
 }
 
 // x^e (e >= 2) from the LDS table, from the table's highest power times x,
 // or by binary powering
 template <int L>
 __device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, int v, int e, const C<L>& xv) {
-  if (e >= S.tab_first && e <= S.tab_last) return load_planar<L>(tab_block<L>(S, tab, e), S.n, v);
+  if (e >= S.tab_first && e <= S.tab_last) return load_planar<L>(tab_block<L>(S, tab, e), tab_cols(S), v);
   if (e == S.tab_last + 1 && S.tab_last >= S.tab_first && S.tab_last >= 2)
-    return c_mul(load_planar<L>(tab_block<L>(S, tab, S.tab_last), S.n, v), xv);
+    return c_mul(load_planar<L>(tab_block<L>(S, tab, S.tab_last), tab_cols(S), v), xv);
   return c_pow(xv, e);
 }
 
-// x_v for a gathered variable: from the LDS table when it holds x
+// x_v for a gathered variable (v = n: the constant 1): from the LDS table
+// when it holds x
 template <int L>
 __device__ __forceinline__ C<L> load_x(const SysView& S, const double* __restrict__ xpt, const double* tab, int v) {
-  if (S.tab_first == 1 && S.tab_last >= 1) return load_planar<L>(tab, S.n, v);
-  return load_planar<L>(xpt, S.n, v);
+  if (S.tab_first == 1 && S.tab_last >= 1) return load_planar<L>(tab, tab_cols(S), v);
+  return v < S.n ? load_planar<L>(xpt, S.n, v) : c_one<L>();
 }
 
-// Build the power table x_v^e, e = tab_first..tab_last, for the point in LDS.
+// value of column v = threadIdx.x of the power table's first block (x_v, or 1
+// for v = n), loaded ahead of the table build
+template <int L>
+__device__ __forceinline__ C<L> table_first_x(const SysView& S, const double* __restrict__ xpt) {
+  if (tab_entries(S) == 0 || int(threadIdx.x) >= S.n) return c_one<L>();
+  return load_planar<L>(xpt, S.n, int(threadIdx.x));
+}
+
+// Build the power table x_v^e, e = tab_first..tab_last, v = 0..n (x_n = 1),
+// for the point in LDS; x0 = table_first_x(S, xpt).
 template <int L, int T>
-__device__ void build_power_table(const SysView& S, const double* __restrict__ xpt, double* tab) {
+__device__ void build_power_table(const SysView& S, const double* __restrict__ xpt, double* tab, const C<L>& x0) {
   if (tab_entries(S) == 0) return;
-  for (int v = threadIdx.x; v < S.n; v += T) {
-    const C<L> x1 = load_planar<L>(xpt, S.n, v);
+  for (int v = threadIdx.x; v <= S.n; v += T) {
+    const C<L> x1 = v == int(threadIdx.x) ? x0 : (v < S.n ? load_planar<L>(xpt, S.n, v) : c_one<L>());
     C<L> p = x1;
     for (int e = 1; e <= S.tab_last; ++e) {
       if (e > 1) p = c_mul(p, x1);
-      if (e >= S.tab_first) store_planar(const_cast<double*>(tab_block<L>(S, tab, e)), S.n, v, p);
+      if (e >= S.tab_first) store_planar(const_cast<double*>(tab_block<L>(S, tab, e)), tab_cols(S), v, p);
     }
   }
 }
@@ -194,19 +215,18 @@ __device__ __forceinline__ int sub_group() { return __builtin_amdgcn_readfirstla
 template <int L, int SEG, int CPL>
 struct ChunkLoads {
   ChunkDesc cd;      // wavefront-uniform
-  OccRec rec[SEG];   // the lane's segment (indices clamped into the chunk)
-  uint32_t meta;     // k | F slot << 16 of the lane's monomial
+  OccRec rec[SEG];   // the lane's records (neutral past its segment)
   C<L> coef;         // coefficient on lane 0 of a monomial's group, else 1
   C<L> vp;           // adjoint weight v_p of the chunk's polynomial
   int cb[CPL], ce[CPL];  // slot ranges of the lane's owned columns
 };
 
+// the lane's loads for the chunk with descriptor `cd` (act false: no chunk)
 template <int L, int SEG, int CPL, int MODE>
-__device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool act, int lt,
-                                           const double* __restrict__ vpt, ChunkLoads<L, SEG, CPL>& cl) {
-  const uint32_t chu = uint32_t(__builtin_amdgcn_readfirstlane(int(ch)));
+__device__ __forceinline__ void load_chunk_of(const SysView& S, const ChunkDesc& cd_in, bool act, int lt,
+                                              const double* __restrict__ vpt, ChunkLoads<L, SEG, CPL>& cl) {
   if (act) {
-    cl.cd = S.chunks[chu];
+    cl.cd = cd_in;
   } else {
     cl.cd = ChunkDesc{};
     cl.cd.s = 1;
@@ -215,9 +235,7 @@ __device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool a
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     const int c = lt + cc * kSub;
-    bool use = act && c < S.ncols;
-    if (MODE == MODE_FONLY) use = use && c >= S.fcol;
-    if (MODE == MODE_ADJ) use = use && c < S.n;
+    const bool use = MODE != MODE_FONLY && act && c < S.n;
     cl.cb[cc] = use ? int(S.colptr[cd.colptr_base + c]) : 0;
     cl.ce[cc] = use ? int(S.colptr[cd.colptr_base + c + 1]) : 0;
   }
@@ -225,55 +243,88 @@ __device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool a
   const int g = lt / s;
   const int q = lt & (s - 1);
   const bool active = g < int(cd.count);
-  cl.meta = active ? S.mmeta[cd.mon_base + g] : 0u;
   cl.coef = (active && q == 0) ? load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * (2 * L)) : c_one<L>();
   if (MODE == MODE_ADJ) cl.vp = act ? load_planar<L>(vpt, S.N, cd.poly) : c_zero<L>();
-  // records of lanes past their segment or past the chunk are valid padding
-  if (cd.width > 0) {
-    const int lane_c = min(lt, int(cd.width) - 1);
-    const int segc = cd.seg;
+  // lanes past the chunk's last group get neutral records; records are
+  // moved as 64-bit words (var | exp << 16 | slot << 32)
+  const uint64_t pad = uint64_t(S.n) | (uint64_t(1) << 16) | (uint64_t(cd.nslots) << 32);
+  const int segc = cd.seg;
+  const bool in_chunk = lt < int(cd.width);
+  const uint64_t* occ = reinterpret_cast<const uint64_t*>(S.occ);
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) cl.rec[i] = S.occ[cd.occ_base + size_t(min(i, segc - 1)) * cd.width + lane_c];
-  } else {
-#pragma unroll
-    for (int i = 0; i < SEG; ++i) cl.rec[i] = OccRec{0, 0, 0, 0};
+  for (int i = 0; i < SEG; ++i) {
+    uint64_t r = pad;
+    if (in_chunk) r = occ[cd.occ_base + size_t(min(i, max(segc - 1, 0))) * cd.width + lt];
+    cl.rec[i].var = uint16_t(r);
+    cl.rec[i].exp = uint16_t(r >> 16);
+    cl.rec[i].slot = uint16_t(r >> 32);
+    cl.rec[i].pad = 0;
   }
 }
 
-// Monomial phase of one chunk: writes every contribution of the chunk into
-// its LDS slot (planar, plane stride max_slots).  All lanes of the sub-group
-// call it (the butterfly needs the whole wavefront).  In MODE_ADJ the
-// coefficient of a monomial of polynomial p is multiplied by conj(v_p).
+// the lane's loads for chunk `ch` (wavefront-uniform)
 template <int L, int SEG, int CPL, int MODE>
-__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
-                                                const double* __restrict__ xpt, const double* tab,
-                                                double* contrib) {
+__device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool act, int lt,
+                                           const double* __restrict__ vpt, ChunkLoads<L, SEG, CPL>& cl) {
+  const uint32_t chu = uint32_t(__builtin_amdgcn_readfirstlane(int(ch)));
+  ChunkDesc cd{};
+  if (act) cd = S.chunks[chu];
+  load_chunk_of<L, SEG, CPL, MODE>(S, cd, act, lt, vpt, cl);
+}
+
+// x_v^(d-1) for the common factor when the table holds x and every power
+// needed: x^0 = 1 is column n of the x block
+template <int L>
+__device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* tab, int v, int d) {
+  const int e = d > 1 ? d - 1 : 1;
+  return load_planar<L>(tab_block<L>(S, tab, e), tab_cols(S), d > 1 ? v : S.n);
+}
+
+// Monomial phase of one chunk: writes every partial derivative of the chunk
+// into its LDS slot (planar, plane stride max_slots) and adds the values of
+// the lane's monomials to facc.  All lanes of the sub-group call it (the
+// butterfly needs the whole wavefront).  Every lane walks the chunk's `seg`
+// records (a wavefront-uniform count; short segments are padded with neutral
+// records).  In MODE_ADJ the coefficient of a monomial of polynomial p is
+// multiplied by conj(v_p).
+//
+// FAST: the chunk's segments have exactly SEG records and the power table
+// holds every power the common factors need, so the sweeps have no branches
+// at all and the compiler can interleave the independent product chains.
+template <int L, int SEG, int CPL, int MODE, bool FAST>
+__device__ __forceinline__ void chunk_monomials_body(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
+                                                     const double* __restrict__ xpt, const double* tab,
+                                                     double* contrib, C<L>& facc) {
   const ChunkDesc& cd = cl.cd;
   const int s = cd.s;
   const int g = lt / s;
   const int q = lt & (s - 1);
   const bool active = g < int(cd.count);
-  const int k = int(cl.meta & 0xffffu);
-  const int fslot = int(cl.meta >> 16);
+  const int segc = FAST ? SEG : __builtin_amdgcn_readfirstlane(int(cd.seg));
   C<L> cf = cl.coef;
   if (MODE == MODE_ADJ && active && q == 0) cf = c_mul(cf, c_conj(cl.vp));
-  const int base = k / s, extra = k - base * s;
-  const int len = base + (q < extra ? 1 : 0);
   const int ms = S.max_slots;
+  const bool full = FAST || tab_full(S);
 
   // every gather of the segment before any arithmetic, so that the LDS
   // latencies overlap
   C<L> xv[SEG];
 #pragma unroll
-  for (int i = 0; i < SEG; ++i) xv[i] = load_x<L>(S, xpt, tab, cl.rec[i].var);
+  for (int i = 0; i < SEG; ++i)
+    xv[i] = (FAST || i < segc) ? (FAST ? load_planar<L>(tab, tab_cols(S), cl.rec[i].var) : load_x<L>(S, xpt, tab, cl.rec[i].var))
+                               : c_one<L>();
 
   C<L> pre[SEG > 1 ? SEG - 1 : 1];
   C<L> A = c_one<L>();
 #pragma unroll
   for (int i = 0; i < SEG; ++i) {
-    if (i < len) {
+    if (FAST || i < segc) {
       const int v = cl.rec[i].var, d = cl.rec[i].exp;
-      if (d >= 2) cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
+      if (full) {
+        cf = c_mul(cf, cf_factor_full<L>(S, tab, v, d));
+      } else if (d >= 2) {
+        cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
+      }
       if (i == 0)
         A = xv[0];
       else
@@ -295,34 +346,90 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoa
   }
   if (MODE == MODE_FONLY) {
     // B is now the monomial's value on every lane of the group
-    if (active && q == 0) store_planar(contrib, ms, fslot, B);
+    if (active && q == 0) facc = c_add(facc, B);
     return;
   }
   // reverse sweep of Speelpenning's product over the segment
   C<L> Sx = (s > 1) ? c_mul(cf, E) : cf;
 #pragma unroll
   for (int i = SEG - 1; i >= 1; --i) {
-    if (i < len) {
+    if (FAST || i < segc) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
       store_planar(contrib, ms, cl.rec[i].slot, c_mul_d(gi, double(cl.rec[i].exp)));
     }
   }
-  if (len >= 1) {
+  if (FAST || segc >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
     store_planar(contrib, ms, cl.rec[0].slot, c_mul_d(g0, double(cl.rec[0].exp)));
   }
-  if (MODE == MODE_EVAL && active && q == 0) store_planar(contrib, ms, fslot, Sx);
+  if (MODE == MODE_EVAL && active && q == 0) facc = c_add(facc, Sx);
 }
 
-// Owner phase: add the chunk's slots into the register accumulators, four
-// slots per step as acc + ((a + b) + (c + d)) (the tail one by one), so that
-// the loads of a step are in flight together and the additions form short
-// chains.  The order depends only on the slot layout.
+template <int L, int SEG, int CPL, int MODE>
+__device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
+                                                const double* __restrict__ xpt, const double* tab,
+                                                double* contrib, C<L>& facc) {
+  if (int(cl.cd.seg) == SEG && tab_full(S))
+    chunk_monomials_body<L, SEG, CPL, MODE, true>(S, cl, lt, xpt, tab, contrib, facc);
+  else
+    chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
+}
+
+// Double-double column sum: compensated summation (Ogita, Rump and Oishi's
+// Sum2 carried to double-double inputs): the high parts go through TwoSum,
+// whose errors and the low parts are added in a plain running sum, and the
+// pair is renormalized once at the end.  For m terms the error is about
+// m^2 u^2 times the sum of their absolute values (u = 2^-53), far inside the
+// double-double bound for the column lengths of a chunk, and the only serial
+// dependence is one addition per slot.
+__device__ __forceinline__ void dd_sum_slots(double& hi, double& lo, const double* __restrict__ phi,
+                                             const double* __restrict__ plo, int b, int e) {
+  int sl = b;
+  for (; sl + 3 < e; sl += 4) {
+    double h[4], l[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      h[j] = phi[sl + j];
+      l[j] = plo[sl + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double s, err;
+      two_sum(hi, h[j], s, err);
+      hi = s;
+      lo += err + l[j];
+    }
+  }
+  for (; sl < e; ++sl) {
+    double s, err;
+    two_sum(hi, phi[sl], s, err);
+    hi = s;
+    lo += err + plo[sl];
+  }
+}
+
+// Owner phase: add the chunk's slots into the register accumulators in slot
+// order.  Double-double uses the compensated sum above; the other levels add
+// four slots per step as acc + ((a + b) + (c + d)) (the tail one by one), so
+// that the loads of a step are in flight together and the additions form
+// short chains.  The order depends only on the slot layout.
 template <int L, int CPL>
 __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&ce)[CPL], const double* contrib,
                                              int ms, C<L> (&acc)[CPL]) {
+  if constexpr (L == 2) {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      if (cb[cc] >= ce[cc]) continue;
+      double rh = acc[cc].re.x[0], rl = acc[cc].re.x[1], ih = acc[cc].im.x[0], il = acc[cc].im.x[1];
+      dd_sum_slots(rh, rl, contrib, contrib + ms, cb[cc], ce[cc]);
+      dd_sum_slots(ih, il, contrib + 2 * ms, contrib + 3 * ms, cb[cc], ce[cc]);
+      two_sum(rh, rl, acc[cc].re.x[0], acc[cc].re.x[1]);
+      two_sum(ih, il, acc[cc].im.x[0], acc[cc].im.x[1]);
+    }
+    return;
+  }
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     int sl = cb[cc];
@@ -337,20 +444,42 @@ __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&c
   }
 }
 
+// F: each wavefront adds its lanes' running sums pairwise and stores the
+// result as its F partial (fpart[w], planar with plane stride kMaxWaves)
+constexpr int kMaxWaves = 16;
+
+template <int L>
+__device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
+  C<L> f = facc;
+  for (int m = 1; m < 64; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
+  if ((threadIdx.x & 63) == 0) store_planar(fpart, kMaxWaves, w, f);
+}
+
 // Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
 // ch0 + sg, ch0 + sg + G, ...  `cl` holds the loads of the sub-group's first
 // chunk, issued by the caller; the loads of each next chunk are issued before
-// the owner phase of the current one.
+// the owner phase of the current one.  After the monomial phase of the last
+// chunk (before the barrier the fast wavefronts wait at anyway) every
+// wavefront stores its F partial, unless fpart is null.  F-only evaluation
+// writes no slots and needs no barriers here.
 template <int L, int SEG, int CPL, int G, int MODE>
 __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1,
                                                const double* __restrict__ xpt, const double* __restrict__ vpt,
                                                const double* tab, double* contrib_base, C<L> (&acc)[CPL],
-                                               ChunkLoads<L, SEG, CPL>& cl) {
+                                               double* fpart, ChunkLoads<L, SEG, CPL>& cl) {
   const int sg = sub_group();
   const int lt = int(threadIdx.x) - sg * kSub;
   double* contrib = contrib_base + size_t(sg) * S.max_slots * 2 * L;
+  C<L> facc = c_zero<L>();
+  if (MODE != MODE_ADJ && fpart && ch0 >= ch1) store_wave_f(facc, fpart);
   for (uint32_t base = ch0; base < ch1; base += G) {
-    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib);
+    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib, facc);
+    if (MODE != MODE_ADJ && fpart && base + G >= ch1) store_wave_f(facc, fpart);
+    if (MODE == MODE_FONLY) {
+      if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+      continue;
+    }
     __syncthreads();
     int cb[CPL], ce[CPL];
 #pragma unroll
@@ -364,79 +493,58 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
   }
 }
 
-// Write row p of J and F from the accumulators (EVAL / FONLY).  With G > 1
-// sub-groups 1..G-1 first hand their partial rows to sub-group 0 through
-// LDS (the contribution regions are free by then), which adds them in order.
-// No LDS is in use when it returns.
+// LDS layout of a workgroup: [power table][G contribution regions][F partials
+// of the 4G wavefronts]
+template <int L>
+__host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int G) {
+  const size_t tab = tab_last >= tab_first ? size_t(tab_last - tab_first + 1) * (n + 1) : 0;
+  return (tab + size_t(G) * max_slots + kMaxWaves) * 2 * L * sizeof(double);
+}
+
+__device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
+  return size_t(tab_entries(S)) * tab_cols(S) * 2 * L;
+}
+
+// Write row p of J and F (EVAL / FONLY).  F: the first thread of the last
+// wavefront adds the wavefronts' F partials (fpart, stored by
+// process_chunks) in order.  J: with G > 1 sub-groups 1..G-1 first hand
+// their partial rows to sub-group 0 through LDS (the contribution regions
+// are free by then), which adds them in order.
 template <int L, int CPL, int G, int MODE>
 __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, int pt, int p, C<L> (&acc)[CPL],
-                                          double* scratch) {
+                                          double* scratch, const double* fpart) {
   const int sg = sub_group();
   const int lt = int(threadIdx.x) - sg * kSub;
-  if (G > 1) {
-    if (sg > 0) {
+  if (MODE == MODE_EVAL && G > 1 && sg > 0) {
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) {
-        const int c = lt + cc * kSub;
-        if (c < S.ncols) store_planar(scratch + size_t(sg - 1) * (2 * L) * S.ncols, S.ncols, c, acc[cc]);
-      }
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int c = lt + cc * kSub;
+      if (c < S.n) store_planar(scratch + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
     }
-    __syncthreads();
-    if (sg == 0) {
+  }
+  __syncthreads();
+  if (MODE == MODE_EVAL && sg == 0) {
+    if (G > 1) {
       for (int o = 1; o < G; ++o) {
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           const int c = lt + cc * kSub;
-          if (c < S.ncols)
-            acc[cc] = c_add(acc[cc], load_planar<L>(scratch + size_t(o - 1) * (2 * L) * S.ncols, S.ncols, c));
+          if (c < S.n) acc[cc] = c_add(acc[cc], load_planar<L>(scratch + size_t(o - 1) * (2 * L) * S.n, S.n, c));
         }
       }
     }
-  }
-  if (sg != 0) return;
-  if (MODE == MODE_EVAL) {
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
       if (c < S.n) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
     }
   }
-  // F = sum of the R partial columns.  They lie in one aligned block of 64
-  // columns, so one wavefront of sub-group 0 holds them all: partial r is
-  // rotated to lane r, and lanes 0..31 are added pairwise.
-  const int fcc = S.fcol / kSub;
-  if (lt / 64 == (S.fcol % kSub) / 64) {
-    const int lane = lt & 63;
-    const int off = S.fcol & 63;
-    C<L> v = c_zero<L>();
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc)
-      if (cc == fcc) v = acc[cc];
-    if (lane < off || lane >= off + S.R) v = c_zero<L>();
-    C<L> f;
-    const int src = (lane + off) & 63;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-      f.re.x[l] = __shfl(v.re.x[l], src);
-      f.im.x[l] = __shfl(v.im.x[l], src);
-    }
-    for (int m = 1; m < 32; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
-    if (lane == 0) {
-      if (O.f_sign < 0) f = c_neg(f);
-      store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, f);
-    }
+  if (int(threadIdx.x) == (4 * G - 1) * 64) {
+    C<L> F = load_planar<L>(fpart, kMaxWaves, 0);
+    for (int o = 1; o < 4 * G; ++o) F = c_add(F, load_planar<L>(fpart, kMaxWaves, o));
+    if (O.f_sign < 0) F = c_neg(F);
+    store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, F);
   }
-}
-
-// LDS layout of a workgroup: [power table][G contribution regions]
-template <int L>
-__host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int G) {
-  const size_t tab = tab_last >= tab_first ? size_t(tab_last - tab_first + 1) * n : 0;
-  return (tab + size_t(G) * max_slots) * 2 * L * sizeof(double);
-}
-
-__device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
-  return size_t(tab_entries(S)) * S.n * 2 * L;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -446,23 +554,31 @@ __device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
 template <int L, int SEG, int CPL, int G, int MODE>
 __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
                                                              int64_t x_pt) {
+  static_assert(G <= kRowDesc, "the first chunk of every sub-group comes from the row-ordered descriptors");
+  static_assert(4 * G <= kMaxWaves, "F partials region");
   extern __shared__ double lds[];
   const int pt = blockIdx.x / S.N;
   const int p = blockIdx.x - pt * S.N;
   const double* xpt = x + pt * x_pt;
   double* tab = lds;
   double* contrib = lds + tab_doubles(S, L);
+  double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
+  // loads first, in the order they are needed: x for the table, the row's
+  // first chunk descriptors (row-ordered copy, no dependence on chunk_ptr),
+  // then the lane's records; the table is built while they are in flight
+  const C<L> x0 = table_first_x<L>(S, xpt);
   const int sg = sub_group();
-  const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
+  const ChunkDesc cd0 = S.rowdesc[size_t(p) * kRowDesc + sg];
   ChunkLoads<L, SEG, CPL> cl;
-  load_chunk<L, SEG, CPL, MODE>(S, ch0 + sg, ch0 + sg < ch1, int(threadIdx.x) - sg * kSub, nullptr, cl);
-  build_power_table<L, G * kSub>(S, xpt, tab);
+  load_chunk_of<L, SEG, CPL, MODE>(S, cd0, cd0.count > 0, int(threadIdx.x) - sg * kSub, nullptr, cl);
+  const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
+  build_power_table<L, G * kSub>(S, xpt, tab, x0);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, cl);
-  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib);
+  process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
+  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
 }
 
 // Adjoint: grid P * NG workgroups of 256 threads; group gi covers
@@ -483,13 +599,14 @@ __global__ __launch_bounds__(kSub) void adjoint_rows_kernel(SysView S, const dou
   const int p1 = min(S.N, p0 + gsize);
   const uint32_t ch0 = S.chunk_ptr[p0], ch1 = S.chunk_ptr[p1];
   ChunkLoads<L, SEG, CPL> cl;
+  const C<L> x0 = table_first_x<L>(S, xpt);
   load_chunk<L, SEG, CPL, MODE_ADJ>(S, ch0, ch0 < ch1, int(threadIdx.x), vpt, cl);
-  build_power_table<L, kSub>(S, xpt, tab);
+  build_power_table<L, kSub>(S, xpt, tab, x0);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, ch0, ch1, xpt, vpt, tab, contrib, acc, cl);
+  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, ch0, ch1, xpt, vpt, tab, contrib, acc, nullptr, cl);
   double* out = part + size_t(pt * NG + gi) * 2 * L * S.n;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
@@ -574,18 +691,20 @@ __global__ __launch_bounds__(kSub) void batch_rows_kernel(const SysView* __restr
     }
     double* tab = lds;
     double* contrib = lds + tab_doubles(S, L);
+    double* fpart = contrib + size_t(S.max_slots) * 2 * L;
     const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
     for (int pt = 0; pt < P; ++pt) {
       const double* xpt = x + x_off[s] * P + int64_t(pt) * 2 * L * n;
+      const C<L> x0 = table_first_x<L>(S, xpt);
       ChunkLoads<L, SEG, CPL> cl;
       load_chunk<L, SEG, CPL, MODE>(S, ch0, ch0 < ch1, int(threadIdx.x), nullptr, cl);
-      build_power_table<L, kSub>(S, xpt, tab);
+      build_power_table<L, kSub>(S, xpt, tab, x0);
       __syncthreads();
       C<L> acc[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-      process_chunks<L, SEG, CPL, 1, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, cl);
-      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib);
+      process_chunks<L, SEG, CPL, 1, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
+      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib, fpart);
     }
   }
 }

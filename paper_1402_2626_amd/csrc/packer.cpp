@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <vector>
 
 namespace pe {
 
@@ -140,23 +141,6 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
     msg = "monomial too large for the segment length";
     return kEunsupported;
   }
-  const double kavg = M > 0 ? double(nnz) / double(M) : 1.0;
-
-  // R partial sums of F: about as many terms per F column as per J column
-  int R = pp.fcols;
-  if (R <= 0) {
-    R = int(double(n) / std::max(kavg, 1.0) + 0.5);
-    R = std::max(1, std::min(R, 32));
-  }
-  out.R = R;
-  // the R partial columns lie inside one aligned block of 64 columns, so
-  // that one wavefront holds all of them when F is summed
-  out.fcol = (n % kMaxWave) + R <= kMaxWave ? n : (n + kMaxWave - 1) / kMaxWave * kMaxWave;
-  out.ncols = out.fcol + R;
-  if (out.ncols + 1 > 65535) {
-    msg = "too many columns";
-    return kEunsupported;
-  }
   const int max_slots = pp.max_slots;
   if (max_slots < kMaxMonomialVars + 1 || max_slots > 65535) {
     msg = "slot budget must be in 1025..65535";
@@ -172,10 +156,10 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
   std::vector<Occ> occ_sorted;
   struct Contrib {
     int col, g, r;
-    int32_t key_slot;  // index into per-chunk arrays
   };
   std::vector<Contrib> contribs;
   std::vector<int> counts;
+  std::vector<std::vector<int>> slot_of;
 
   int64_t packed_t = 0;
   for (int p = 0; p < N; ++p) {
@@ -192,12 +176,14 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
       const int kfirst = int(in.mon_ptr[order[i] + 1] - in.mon_ptr[order[i]]);
       const int s = lanes_for(std::max(kfirst, 1), seg);
       const int cap = T / s;
+      // one slot per partial derivative; slot index `slots` (one past the
+      // last) is the chunk's dummy slot, so at most max_slots - 1 are used
       int count = 0, slots = 0;
       size_t j = i;
       while (j < order.size() && count < cap) {
         const int k = int(in.mon_ptr[order[j] + 1] - in.mon_ptr[order[j]]);
         if (slots + k + 1 > max_slots) break;
-        slots += k + 1;
+        slots += k;
         ++count;
         ++j;
       }
@@ -212,7 +198,7 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
       const int segc = kfirst > 0 ? (kfirst + s - 1) / s : 1;
       cd.seg = uint8_t(segc);
       out.max_seg_used = std::max(out.max_seg_used, segc);
-      out.max_slots_used = std::max(out.max_slots_used, slots);
+      out.max_slots_used = std::max(out.max_slots_used, slots + 1);
       cd.occ_base = uint32_t(out.occ.size());
       if (out.occ.size() + size_t(segc) * cd.width > (size_t(1) << 32)) {
         msg = "packed occurrence array too large";
@@ -222,44 +208,37 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
 
       // contributions: (column, monomial in chunk, position) -> slot
       contribs.clear();
+      slot_of.resize(size_t(count));
       for (int g = 0; g < count; ++g) {
         const int64_t t = order[i + g];
         const int64_t a = in.mon_ptr[t], b = in.mon_ptr[t + 1];
         occ_sorted.clear();
         for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o]});
         std::sort(occ_sorted.begin(), occ_sorted.end(), [](const Occ& x, const Occ& y) { return x.var < y.var; });
-        for (int r = 0; r < int(occ_sorted.size()); ++r) contribs.push_back({occ_sorted[r].var, g, r, 0});
-        contribs.push_back({out.fcol + g % R, g, 1 << 20, 0});
+        for (int r = 0; r < int(occ_sorted.size()); ++r) contribs.push_back({occ_sorted[r].var, g, r});
+        slot_of[size_t(g)].assign(occ_sorted.size(), 0);
       }
-      std::vector<Contrib> sorted = contribs;
-      std::stable_sort(sorted.begin(), sorted.end(), [](const Contrib& x, const Contrib& y) {
+      std::stable_sort(contribs.begin(), contribs.end(), [](const Contrib& x, const Contrib& y) {
         if (x.col != y.col) return x.col < y.col;
         if (x.g != y.g) return x.g < y.g;
         return x.r < y.r;
       });
       // slot of (g, r): position in the sorted list
-      std::vector<std::vector<int>> slot_of;
-      slot_of.resize(size_t(count));
-      std::vector<int> fslot(size_t(count), 0);
-      for (int g = 0; g < count; ++g) {
-        const int64_t t = order[i + g];
-        slot_of[g].assign(size_t(in.mon_ptr[t + 1] - in.mon_ptr[t]), 0);
-      }
-      counts.assign(size_t(out.ncols) + 1, 0);
-      for (int sidx = 0; sidx < int(sorted.size()); ++sidx) {
-        const Contrib& c = sorted[sidx];
-        if (c.r == (1 << 20))
-          fslot[c.g] = sidx;
-        else
-          slot_of[c.g][c.r] = sidx;
+      counts.assign(size_t(n) + 1, 0);
+      for (int sidx = 0; sidx < int(contribs.size()); ++sidx) {
+        const Contrib& c = contribs[size_t(sidx)];
+        slot_of[size_t(c.g)][size_t(c.r)] = sidx;
         counts[size_t(c.col) + 1]++;
       }
-      for (int c = 0; c < out.ncols; ++c) counts[size_t(c) + 1] += counts[size_t(c)];
-      for (int c = 0; c <= out.ncols; ++c) out.colptr.push_back(uint16_t(counts[size_t(c)]));
+      for (int c = 0; c < n; ++c) counts[size_t(c) + 1] += counts[size_t(c)];
+      for (int c = 0; c <= n; ++c) out.colptr.push_back(uint16_t(counts[size_t(c)]));
 
-      // occurrence records, lane-major
+      // occurrence records, lane-major; positions past a lane's segment hold
+      // the neutral record (variable n, whose value is 1, exponent 1, the
+      // dummy slot)
       const size_t rec0 = out.occ.size();
-      out.occ.resize(rec0 + size_t(segc) * cd.width, OccRec{0, 0, 0, 0});
+      const OccRec pad{uint16_t(n), 1, uint16_t(slots), 0};
+      out.occ.resize(rec0 + size_t(segc) * cd.width, pad);
       int64_t cost = 0;
       for (int g = 0; g < count; ++g) {
         const int64_t t = order[i + g];
@@ -278,14 +257,14 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
             OccRec& rec = out.occ[rec0 + size_t(ii) * cd.width + size_t(lane)];
             rec.var = uint16_t(oc.var);
             rec.exp = uint16_t(oc.exp);
-            rec.slot = uint16_t(slot_of[g][r0 + ii]);
+            rec.slot = uint16_t(slot_of[size_t(g)][size_t(r0 + ii)]);
           }
         }
         // packed monomial: coefficient and metadata
         for (int c = 0; c < 2; ++c)
           for (int l = 0; l < L; ++l)
             out.mcoef[size_t(packed_t + g) * 2 * L + size_t(c) * L + l] = in.coef[(size_t(c) * L + l) * size_t(M) + size_t(t)];
-        out.mmeta[size_t(packed_t + g)] = mon_meta(uint32_t(k), uint32_t(fslot[g]));
+        out.mmeta[size_t(packed_t + g)] = mon_meta(uint32_t(k));
         cost += k;
       }
       out.poly_cost[p] += int64_t(segc) * s * count + cost;
@@ -295,6 +274,10 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
     }
   }
   out.chunk_ptr[N] = uint32_t(out.chunks.size());
+  out.rowdesc.assign(size_t(N) * kRowDesc, ChunkDesc{});
+  for (int p = 0; p < N; ++p)
+    for (uint32_t j = 0; j < uint32_t(kRowDesc) && out.chunk_ptr[p] + j < out.chunk_ptr[p + 1]; ++j)
+      out.rowdesc[size_t(p) * kRowDesc + j] = out.chunks[out.chunk_ptr[p] + j];
   return kOk;
 }
 

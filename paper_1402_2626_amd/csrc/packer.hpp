@@ -25,24 +25,23 @@ struct SysInput {
 struct PackParams {
   int threads = 256;        // workgroup size T
   int seg = 4;              // largest number of variables per lane
-  int max_slots = 2048;     // LDS contribution slots per chunk
-  int fcols = 0;            // R, partial sums of F (0: choose)
+  int max_slots = 2048;     // LDS contribution slots per chunk, dummy included
 };
 
 struct Packed {
   int level = 0, n = 0, N = 0;
   int64_t M = 0, nnz = 0;
   int emax = 1, kmax = 0;
-  int R = 1, fcol = 1, ncols = 1;  // F partial columns fcol .. fcol+R-1
   PackParams params;
-  int max_slots_used = 0;
+  int max_slots_used = 0;  // largest nslots + 1 (the dummy slot)
   int max_seg_used = 1;
   std::vector<OccRec> occ;
   std::vector<double> mcoef;      // [M][2L], packed monomial order
-  std::vector<uint32_t> mmeta;    // [M]
+  std::vector<uint32_t> mmeta;    // [M], mon_meta
   std::vector<ChunkDesc> chunks;
   std::vector<uint32_t> chunk_ptr;  // [N+1]
-  std::vector<uint16_t> colptr;     // [chunks][ncols+1]
+  std::vector<ChunkDesc> rowdesc;   // [N][kRowDesc]: row p's first chunks, zero (count 0) past its last
+  std::vector<uint16_t> colptr;     // [chunks][n+1]
   std::vector<int64_t> poly_cost;   // [N] relative cost of a polynomial (for scheduling)
 };
 

@@ -235,8 +235,8 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   Plan pl;
   pl.seg = seg;
   pl.max_slots = std::max(H.max_slots_used, 1);
-  pl.cpl = cpl_bucket(H.ncols, kSub);
-  if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 columns (n + R) is not supported");
+  pl.cpl = cpl_bucket(H.n, kSub);
+  if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 variables is not supported");
   const size_t limit = device_lds_limit();
   const int L = H.level;
   auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, G) * L; };
@@ -260,7 +260,7 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
     if (!shape_compiled(L, seg, G)) return false;
     if (pick_table(G) < 0) return false;
     if (G == 1) return true;
-    return pl.cpl <= 2 && H.ncols * (G - 1) <= pl.max_slots * G;
+    return pl.cpl <= 2 && H.n * (G - 1) <= pl.max_slots * G;
   };
   if (force_G > 0) {
     if (!fits(force_G)) return fail(PE_EUNSUPPORTED, "this launch shape does not fit the system");
@@ -332,17 +332,15 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   V = SysView{};
   V.n = P.n;
   V.N = P.N;
-  V.R = P.R;
-  V.fcol = P.fcol;
-  V.ncols = P.ncols;
   V.emax = P.emax;
   V.tab_first = sys->plan.tab_first;
   V.tab_last = sys->plan.tab_last;
   V.max_slots = sys->plan.max_slots;
   pe_status e = PE_OK;
   if ((e = upload(sys, P.chunks, V.chunks, hs)) != PE_OK || (e = upload(sys, P.chunk_ptr, V.chunk_ptr, hs)) != PE_OK ||
+      (e = upload(sys, P.rowdesc, V.rowdesc, hs)) != PE_OK ||
       (e = upload(sys, P.occ, V.occ, hs)) != PE_OK || (e = upload(sys, P.mcoef, V.mcoef, hs)) != PE_OK ||
-      (e = upload(sys, P.mmeta, V.mmeta, hs)) != PE_OK || (e = upload(sys, P.colptr, V.colptr, hs)) != PE_OK)
+      (e = upload(sys, P.colptr, V.colptr, hs)) != PE_OK)
     return e;
   PE_HIP(hipStreamSynchronize(hs));
   // the device copies are authoritative; keep only what batches and tuning need
@@ -793,7 +791,7 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
       delete b;
       return fail(PE_EINVAL, "batched systems must share level, launch shape and device");
     }
-    maxcols = std::max(maxcols, y->view.ncols);
+    maxcols = std::max(maxcols, y->view.n);
     b->lds = std::max(b->lds, y->plan.lds1);
     b->maxN = std::max(b->maxN, y->view.N);
   }

@@ -32,15 +32,26 @@ extern "C" int pe_test_pack(int level, int n, int N, const int64_t* poly_ptr, co
   sizes[1] = int64_t(g_packed.occ.size());
   sizes[2] = int64_t(g_packed.colptr.size());
   sizes[3] = g_packed.M;
-  sizes[4] = g_packed.R;
-  sizes[5] = g_packed.ncols;
-  sizes[6] = g_packed.max_slots_used;
-  sizes[7] = g_packed.emax;
-  sizes[8] = g_packed.fcol;
+  sizes[4] = g_packed.n;
+  sizes[5] = g_packed.max_slots_used;
+  sizes[6] = g_packed.emax;
+  sizes[7] = g_packed.kmax;
+  sizes[8] = 0;
   return 0;
 }
 
 extern "C" const char* pe_test_pack_msg() { return g_msg.c_str(); }
+
+// row-ordered first descriptors as 9 int64 each, kRowDesc per row
+extern "C" int pe_test_pack_rowdesc(int64_t* out) {
+  for (size_t i = 0; i < g_packed.rowdesc.size(); ++i) {
+    const ChunkDesc& c = g_packed.rowdesc[i];
+    int64_t* o = out + 9 * i;
+    o[0] = c.occ_base; o[1] = c.mon_base; o[2] = c.colptr_base; o[3] = c.poly; o[4] = c.count;
+    o[5] = c.nslots; o[6] = c.width; o[7] = c.s; o[8] = c.seg;
+  }
+  return kRowDesc;
+}
 
 // chunks as 9 int64 each: occ_base, mon_base, colptr_base, poly, count, nslots, width, s, seg
 extern "C" void pe_test_pack_get(int64_t* chunks, uint16_t* occ /* [occ][4] */, uint16_t* colptr, uint32_t* mmeta,

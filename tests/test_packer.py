@@ -37,8 +37,22 @@ def pack(lib, s, seg, max_slots=1152):
     mcoef = np.zeros(M * 2 * s.level)
     cptr = np.zeros(s.n_polys + 1, np.uint32)
     lib.pe_test_pack_get(*[ctypes.c_void_p(a.ctypes.data) for a in (chunks, occ, colptr, mmeta, mcoef, cptr)])
-    return dict(chunks=chunks, occ=occ, colptr=colptr, mmeta=mmeta, mcoef=mcoef, chunk_ptr=cptr, R=int(sizes[4]),
-                ncols=int(sizes[5]), max_slots_used=int(sizes[6]), fcol=int(sizes[8]))
+    rowdesc = np.zeros((s.n_polys * 4, 9), np.int64)
+    assert lib.pe_test_pack_rowdesc(ctypes.c_void_p(rowdesc.ctypes.data)) == 4
+    return dict(chunks=chunks, occ=occ, colptr=colptr, mmeta=mmeta, mcoef=mcoef, chunk_ptr=cptr, rowdesc=rowdesc,
+                n=int(sizes[4]), max_slots_used=int(sizes[5]))
+
+
+def check_rowdesc(P, n_polys):
+    # row p's first four chunk descriptors in row order, empty (count 0) past the row's last chunk
+    for p in range(n_polys):
+        c0, c1 = int(P["chunk_ptr"][p]), int(P["chunk_ptr"][p + 1])
+        for j in range(4):
+            got = P["rowdesc"][p * 4 + j]
+            if c0 + j < c1:
+                assert np.array_equal(got, P["chunks"][c0 + j])
+            else:
+                assert got[4] == 0
 
 
 def lanes_for(k, seg):
@@ -68,10 +82,8 @@ def test_pack_invariants(lib, seg):
     coef = synth.unit_circle(rng, sum(len(m) for m in polys), 2)
     s = synth.from_monomial_lists(2, 60, polys, coef_limbs=coef)
     P = pack(lib, s, seg)
-    ncols, R, fcol = P["ncols"], P["R"], P["fcol"]
-    # the F partial columns sit in one aligned block of 64 columns
-    assert fcol >= 60 and ncols == fcol + R and fcol // 64 == (fcol + R - 1) // 64
-    assert fcol == (60 if 60 % 64 + R <= 64 else 64)
+    n = P["n"]
+    assert n == 60
     seen_mon = set()
     for p in range(s.n_polys):
         # monomials of polynomial p, as multisets of (var, exp)
@@ -81,23 +93,24 @@ def test_pack_invariants(lib, seg):
         for ch in range(int(P["chunk_ptr"][p]), int(P["chunk_ptr"][p + 1])):
             ob, mb, cb, poly, count, nslots, width, sl, segc = P["chunks"][ch]
             assert poly == p and width == count * sl and sl <= 64 and segc <= seg
-            cp = P["colptr"][cb:cb + ncols + 1].astype(int)
+            assert nslots + 1 <= P["max_slots_used"]
+            cp = P["colptr"][cb:cb + n + 1].astype(int)
             assert cp[0] == 0 and cp[-1] == nslots and np.all(np.diff(cp) >= 0)
-            col_of_slot = np.repeat(np.arange(ncols), np.diff(cp))
-            assert np.all(np.diff(cp)[60:fcol] == 0)  # no slots between the J and F columns
+            col_of_slot = np.repeat(np.arange(n), np.diff(cp))
             slots = []
             for g in range(count):
-                meta = int(P["mmeta"][mb + g])
-                k, fslot = meta & 0xFFFF, meta >> 16
-                assert lanes_for(max(k, 1), seg) <= sl
-                assert col_of_slot[fslot] == fcol + g % R
-                slots.append(fslot)
+                k = int(P["mmeta"][mb + g])
+                assert lanes_for(max(k, 1), seg) <= sl and k <= sl * segc
                 occs = []
                 base, extra = k // sl, k % sl
                 for q in range(sl):
                     ln = base + (1 if q < extra else 0)
-                    for i in range(ln):
+                    for i in range(segc):
                         var, ex, slot, _ = P["occ"][ob + i * width + g * sl + q]
+                        if i >= ln:
+                            # neutral padding: the constant-1 column, exponent 1, the dummy slot
+                            assert (var, ex, slot) == (n, 1, nslots)
+                            continue
                         occs.append((int(var), int(ex)))
                         assert col_of_slot[slot] == var
                         slots.append(int(slot))
@@ -106,16 +119,18 @@ def test_pack_invariants(lib, seg):
                 seen_mon.add(mb + g)
             assert sorted(slots) == list(range(nslots)), "slots must be a permutation"
             # within a column, slots follow (monomial, position) order
-            for c in range(ncols):
+            for c in range(n):
                 seg_slots = list(range(cp[c], cp[c + 1]))
                 assert seg_slots == sorted(seg_slots)
         assert sorted(got) == want
     assert len(seen_mon) == s.n_monomials
+    check_rowdesc(P, s.n_polys)
 
 
 def test_chunk_budget(lib):
     s = synth.random_system(9, 4, n_vars=300, n_polys=2, m=500, k=20, exp_lo=1, exp_hi=2)
     P = pack(lib, s, 4, max_slots=1100)
     assert P["max_slots_used"] <= 1100
-    assert np.all(P["chunks"][:, 5] <= 1100)
+    assert np.all(P["chunks"][:, 5] + 1 <= 1100)
     assert np.all(P["chunks"][:, 6] <= 256)
+    check_rowdesc(P, s.n_polys)
