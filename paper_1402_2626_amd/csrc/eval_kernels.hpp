@@ -272,6 +272,25 @@ __device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool a
   load_chunk_of<L, SEG, CPL, MODE>(S, cd, act, lt, vpt, cl);
 }
 
+// A partial derivative times its exponent d (a small positive integer).
+// Double-double leaves the product unnormalized, (p, e) with p = fl(hi d) and
+// e = the exact error of that product plus lo d: |e| stays within about one
+// unit in the last place of p, which every consumer of a slot (the owners'
+// compensated sums, the double-double additions) accepts.
+template <int L>
+__device__ __forceinline__ C<L> scale_by_exponent(const C<L>& a, double d) {
+  if constexpr (L == 2) {
+    C<2> r;
+    r.re.x[0] = a.re.x[0] * d;
+    r.re.x[1] = PE_FMA(a.re.x[1], d, PE_FMA(a.re.x[0], d, -r.re.x[0]));
+    r.im.x[0] = a.im.x[0] * d;
+    r.im.x[1] = PE_FMA(a.im.x[1], d, PE_FMA(a.im.x[0], d, -r.im.x[0]));
+    return r;
+  } else {
+    return c_mul_d(a, d);
+  }
+}
+
 // x_v^(d-1) for the common factor when the table holds x and every power
 // needed: x^0 = 1 is column n of the x block
 template <int L>
@@ -356,13 +375,13 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
     if (FAST || i < segc) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      store_planar(contrib, ms, cl.rec[i].slot, c_mul_d(gi, double(cl.rec[i].exp)));
+      store_planar(contrib, ms, cl.rec[i].slot, scale_by_exponent(gi, double(cl.rec[i].exp)));
     }
   }
   if (FAST || segc >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    store_planar(contrib, ms, cl.rec[0].slot, c_mul_d(g0, double(cl.rec[0].exp)));
+    store_planar(contrib, ms, cl.rec[0].slot, scale_by_exponent(g0, double(cl.rec[0].exp)));
   }
   if (MODE == MODE_EVAL && active && q == 0) facc = c_add(facc, Sx);
 }
@@ -451,7 +470,26 @@ constexpr int kMaxWaves = 16;
 template <int L>
 __device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
   C<L> f = facc;
-  for (int m = 1; m < 64; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
+  if constexpr (L == 2) {
+    // double-double: TwoSum on the high parts, low parts and errors in a
+    // plain sum, renormalized once (the compensated summation of the owners)
+    double rh = f.re.x[0], rl = f.re.x[1], ih = f.im.x[0], il = f.im.x[1];
+    for (int m = 1; m < 64; m <<= 1) {
+      const double orh = __shfl_xor(rh, m), orl = __shfl_xor(rl, m);
+      const double oih = __shfl_xor(ih, m), oil = __shfl_xor(il, m);
+      double s, e;
+      two_sum(rh, orh, s, e);
+      rh = s;
+      rl = (rl + orl) + e;
+      two_sum(ih, oih, s, e);
+      ih = s;
+      il = (il + oil) + e;
+    }
+    two_sum(rh, rl, f.re.x[0], f.re.x[1]);
+    two_sum(ih, il, f.im.x[0], f.im.x[1]);
+  } else {
+    for (int m = 1; m < 64; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
+  }
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
   if ((threadIdx.x & 63) == 0) store_planar(fpart, kMaxWaves, w, f);
 }
