@@ -38,6 +38,34 @@ def describe(name):
             f"exps {{1..{w['exp_hi']}}}, {w['P']} point(s)")
 PEAK_FP64_TFLOPS = 78.6  # 256 CUs x 64 FP64 FMA lanes/clk x 2 flops x 2.4 GHz
 
+# HBM bytes of the evaluation kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes (KiB per dispatch) scaled by what the same counters read for a plain
+# device copy of known size.  The figures hold for the kernel sources they
+# were taken with: `traffic` is null when the sources have changed since.
+COUNTERS = os.path.join(ROOT, "profiles", "eval_rows_dd_n256_counters.json")
+KERNEL_SOURCES = ["eval_kernels.hpp", "mdarith.hpp", "layout.hpp", "polyeval.hip", "packer.cpp", "packer.hpp"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1402_2626_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per launch of the evaluation kernel, or None."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("workload") != workload or c.get("source_sha256") != kernel_source_digest():
+        return None
+    return (c["fetch_kib_per_dispatch"] * c["fetch_scale"] + c["write_kib_per_dispatch"] * c["write_scale"]) * 1024.0
+
 
 def cpu_baseline(sys_, x, rows: int):
     """The exact oracle on the first `rows` polynomials (F and full rows of
@@ -140,22 +168,11 @@ def main():
         S.eval(xd, out=(F, J), stream=stream)
     torch.cuda.synchronize()
 
-    # timed region: K steps, each one pe_eval (one kernel launch)
+    # timed region: K steps, each one pe_eval (one kernel launch), enqueued
+    # back to back; HIP events on the launch stream bracket the region, so
+    # their interval / K is the average launch duration
     K = args.steps
-    t0 = time.perf_counter()
-    for _ in range(K):
-        S.eval(xd, out=(F, J), stream=stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    # kernel duration with events on the launch stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    for a, b in ev:
-        a.record(stream)
-        S.eval(xd, out=(F, J), stream=stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / K
+    dt, kern_ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=stream), K, 0, stream)
 
     M = sys_.n_monomials
     flops = W.flops_per_point(sys_) * P
@@ -177,7 +194,7 @@ def main():
                    "points": P, "monomials": M, "occurrences": sys_.nnz,
                    "F_plus_J_per_s": P * K / dt, "kernel_ms": kern_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": counter_traffic(args.workload)},
         "cpu_baseline": cpu,
     }
     S.close()
@@ -185,22 +202,22 @@ def main():
 
 
 def _time_steps(fn, K, W, stream):
+    """W untimed calls, then K timed calls enqueued back to back.  Returns the
+    wall time of the K calls (synchronised on both sides) and the average
+    per-call time from HIP events recorded on `stream` around them."""
     import torch
     for _ in range(W):
         fn()
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record(stream)
     for _ in range(K):
         fn()
+    e1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    for a, b in ev:
-        a.record(stream)
-        fn()
-        b.record(stream)
-    torch.cuda.synchronize()
-    return dt, sum(a.elapsed_time(b) for a, b in ev) / K
+    return dt, e0.elapsed_time(e1) / K
 
 
 def bench_adjoint(args):

@@ -105,8 +105,13 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[11]);
  * monomials of a row are cut into chunks of 256 lanes, and a workgroup of
  * chunks_per_workgroup * 256 threads works on that many chunks of a row at
  * once, adding their partial rows in a fixed order.
- *   segment               variables per lane: 8 or 16 (D), 4 or 8 (DD),
- *                         2 or 4 (QD); 0 = the level's default.
+ *   segment               variables per lane: 8 or 16 (D), 4, 6 or 8 (DD),
+ *                         2 or 4 (QD); 0 = the default: the first of 8, 16
+ *                         (D), 8, 6, 4 (DD) or 4, 2 (QD) for which the most
+ *                         common monomial size k is an exact multiple of s
+ *                         filling every lane (k > (segment - 1) * s), else 8
+ *                         (D, DD) or 4 (QD).  pe_system_create starts from
+ *                         the same default.
  *   chunks_per_workgroup  1, 2 or 4 as compiled for the level and segment;
  *                         0 = the largest that fits.
  * A new segment length repacks the system (host work and a device upload
@@ -142,7 +147,8 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
  * A batch evaluates S independent systems of the same level, each at the
  * same number of points, in one persistent launch whose work items
  * (system, point, polynomial) are taken from a device queue in decreasing
- * order of cost.  The systems must outlive the batch. */
+ * order of cost.  The systems must share the level and the segment length
+ * (pe_system_set_shape; PE_EINVAL otherwise) and outlive the batch. */
 pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream);
 pe_status pe_batch_destroy(pe_batch* batch);
 
@@ -152,6 +158,14 @@ pe_status pe_batch_destroy(pe_batch* batch);
  * block is then [P][2][L][n_s] (x), [P][2][L][N_s] (F), [P][2][L][N_s][n_s]
  * (J). */
 pe_status pe_batch_layout(const pe_batch* batch, int64_t* x_off, int64_t* F_off, int64_t* J_off);
+
+/* Shape of the persistent launch: info[0] = S, [1] = level, [2] = segment
+ * length, [3] = chunks per workgroup (2 when compiled for the level and
+ * segment, when some row has two or more chunks and every system fits in
+ * LDS with two slot regions, else 1).  A row evaluated in the batch gives
+ * bitwise the same F and J as pe_eval on its system with that many chunks
+ * per workgroup. */
+pe_status pe_batch_info(const pe_batch* batch, int64_t info[4]);
 
 /* Evaluate every system of the batch at points_per_system points each.
  * x, F, J are device arrays in the packed layout above (J may be NULL).

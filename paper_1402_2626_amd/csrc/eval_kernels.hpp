@@ -106,6 +106,28 @@ __device__ __forceinline__ void store_aos(double* p, const C<L>& v) {
   }
 }
 
+// LDS arrays of complex multi-doubles.  D and DD are planar (component k of
+// element i at base[k * stride + i], components re limbs then im limbs): a
+// wavefront's gather then reads 8-byte words spread over all banks, where
+// 16- or 32-byte records map every lane's access onto a fraction of them.
+// QD keeps one 64-byte record per element (base[i * 8 + k]), which moves the
+// same bytes in half as many LDS instructions and measured faster.
+template <int L>
+__device__ __forceinline__ C<L> lds_ld(const double* base, int stride, int i) {
+  if constexpr (L == 4)
+    return load_aos<L>(base + size_t(i) * (2 * L));
+  else
+    return load_planar<L>(base, stride, i);
+}
+
+template <int L>
+__device__ __forceinline__ void lds_st(double* base, int stride, int i, const C<L>& v) {
+  if constexpr (L == 4)
+    store_aos(base + size_t(i) * (2 * L), v);
+  else
+    store_planar(base, stride, i, v);
+}
+
 template <int L>
 __device__ __forceinline__ C<L> shfl_xor_c(const C<L>& v, int mask) {
   C<L> r;
@@ -134,11 +156,6 @@ __device__ __forceinline__ int tab_entries(const SysView& S) {
   return S.tab_last >= S.tab_first ? S.tab_last - S.tab_first + 1 : 0;
 }
 
-// LDS arrays of complex multi-doubles are planar (component k of element i at
-// base[k * stride + i], components re limbs then im limbs): a wavefront's
-// gather then reads 8-byte words spread over all banks, where 32-byte records
-// would map every lane's access onto the same half of the banks.
-
 // the power table has n + 1 columns: the variables and the constant 1
 __device__ __forceinline__ int tab_cols(const SysView& S) { return S.n + 1; }
 
@@ -158,9 +175,9 @@ __device__ __forceinline__ bool tab_full(const SysView& S) {
 // or by binary powering
 template <int L>
 __device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, int v, int e, const C<L>& xv) {
-  if (e >= S.tab_first && e <= S.tab_last) return load_planar<L>(tab_block<L>(S, tab, e), tab_cols(S), v);
+  if (e >= S.tab_first && e <= S.tab_last) return lds_ld<L>(tab_block<L>(S, tab, e), tab_cols(S), v);
   if (e == S.tab_last + 1 && S.tab_last >= S.tab_first && S.tab_last >= 2)
-    return c_mul(load_planar<L>(tab_block<L>(S, tab, S.tab_last), tab_cols(S), v), xv);
+    return c_mul(lds_ld<L>(tab_block<L>(S, tab, S.tab_last), tab_cols(S), v), xv);
   return c_pow(xv, e);
 }
 
@@ -168,7 +185,7 @@ __device__ __forceinline__ C<L> power_of(const SysView& S, const double* tab, in
 // when it holds x
 template <int L>
 __device__ __forceinline__ C<L> load_x(const SysView& S, const double* __restrict__ xpt, const double* tab, int v) {
-  if (S.tab_first == 1 && S.tab_last >= 1) return load_planar<L>(tab, tab_cols(S), v);
+  if (S.tab_first == 1 && S.tab_last >= 1) return lds_ld<L>(tab, tab_cols(S), v);
   return v < S.n ? load_planar<L>(xpt, S.n, v) : c_one<L>();
 }
 
@@ -190,7 +207,7 @@ __device__ void build_power_table(const SysView& S, const double* __restrict__ x
     C<L> p = x1;
     for (int e = 1; e <= S.tab_last; ++e) {
       if (e > 1) p = c_mul(p, x1);
-      if (e >= S.tab_first) store_planar(const_cast<double*>(tab_block<L>(S, tab, e)), tab_cols(S), v, p);
+      if (e >= S.tab_first) lds_st(const_cast<double*>(tab_block<L>(S, tab, e)), tab_cols(S), v, p);
     }
   }
 }
@@ -296,7 +313,7 @@ __device__ __forceinline__ C<L> scale_by_exponent(const C<L>& a, double d) {
 template <int L>
 __device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* tab, int v, int d) {
   const int e = d > 1 ? d - 1 : 1;
-  return load_planar<L>(tab_block<L>(S, tab, e), tab_cols(S), d > 1 ? v : S.n);
+  return lds_ld<L>(tab_block<L>(S, tab, e), tab_cols(S), d > 1 ? v : S.n);
 }
 
 // Monomial phase of one chunk: writes every partial derivative of the chunk
@@ -330,7 +347,7 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
   C<L> xv[SEG];
 #pragma unroll
   for (int i = 0; i < SEG; ++i)
-    xv[i] = (FAST || i < segc) ? (FAST ? load_planar<L>(tab, tab_cols(S), cl.rec[i].var) : load_x<L>(S, xpt, tab, cl.rec[i].var))
+    xv[i] = (FAST || i < segc) ? (FAST ? lds_ld<L>(tab, tab_cols(S), cl.rec[i].var) : load_x<L>(S, xpt, tab, cl.rec[i].var))
                                : c_one<L>();
 
   C<L> pre[SEG > 1 ? SEG - 1 : 1];
@@ -375,13 +392,13 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
     if (FAST || i < segc) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      store_planar(contrib, ms, cl.rec[i].slot, scale_by_exponent(gi, double(cl.rec[i].exp)));
+      lds_st(contrib, ms, cl.rec[i].slot, scale_by_exponent(gi, double(cl.rec[i].exp)));
     }
   }
   if (FAST || segc >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    store_planar(contrib, ms, cl.rec[0].slot, scale_by_exponent(g0, double(cl.rec[0].exp)));
+    lds_st(contrib, ms, cl.rec[0].slot, scale_by_exponent(g0, double(cl.rec[0].exp)));
   }
   if (MODE == MODE_EVAL && active && q == 0) facc = c_add(facc, Sx);
 }
@@ -453,13 +470,13 @@ __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&c
   for (int cc = 0; cc < CPL; ++cc) {
     int sl = cb[cc];
     for (; sl + 3 < ce[cc]; sl += 4) {
-      const C<L> a = load_planar<L>(contrib, ms, sl);
-      const C<L> b = load_planar<L>(contrib, ms, sl + 1);
-      const C<L> c = load_planar<L>(contrib, ms, sl + 2);
-      const C<L> d = load_planar<L>(contrib, ms, sl + 3);
+      const C<L> a = lds_ld<L>(contrib, ms, sl);
+      const C<L> b = lds_ld<L>(contrib, ms, sl + 1);
+      const C<L> c = lds_ld<L>(contrib, ms, sl + 2);
+      const C<L> d = lds_ld<L>(contrib, ms, sl + 3);
       acc[cc] = c_add(acc[cc], c_add(c_add(a, b), c_add(c, d)));
     }
-    for (; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], load_planar<L>(contrib, ms, sl));
+    for (; sl < ce[cc]; ++sl) acc[cc] = c_add(acc[cc], lds_ld<L>(contrib, ms, sl));
   }
 }
 
@@ -491,7 +508,7 @@ __device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
     for (int m = 1; m < 64; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
   }
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
-  if ((threadIdx.x & 63) == 0) store_planar(fpart, kMaxWaves, w, f);
+  if ((threadIdx.x & 63) == 0) lds_st(fpart, kMaxWaves, w, f);
 }
 
 // Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
@@ -557,7 +574,7 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
-      if (c < S.n) store_planar(scratch + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
+      if (c < S.n) lds_st(scratch + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
     }
   }
   __syncthreads();
@@ -567,7 +584,7 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           const int c = lt + cc * kSub;
-          if (c < S.n) acc[cc] = c_add(acc[cc], load_planar<L>(scratch + size_t(o - 1) * (2 * L) * S.n, S.n, c));
+          if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(scratch + size_t(o - 1) * (2 * L) * S.n, S.n, c));
         }
       }
     }
@@ -578,8 +595,8 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
     }
   }
   if (int(threadIdx.x) == (4 * G - 1) * 64) {
-    C<L> F = load_planar<L>(fpart, kMaxWaves, 0);
-    for (int o = 1; o < 4 * G; ++o) F = c_add(F, load_planar<L>(fpart, kMaxWaves, o));
+    C<L> F = lds_ld<L>(fpart, kMaxWaves, 0);
+    for (int o = 1; o < 4 * G; ++o) F = c_add(F, lds_ld<L>(fpart, kMaxWaves, o));
     if (O.f_sign < 0) F = c_neg(F);
     store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, F);
   }
@@ -682,17 +699,22 @@ __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-// Persistent kernel: workgroups take (system, polynomial) items from a
-// device counter in the order of `items` (decreasing cost) until none is
-// left; each item is evaluated at all P points.  Every workgroup reaches the
-// exit test after every item, so the grid drains.
-template <int L, int SEG, int CPL, int MODE>
-__global__ __launch_bounds__(kSub) void batch_rows_kernel(const SysView* __restrict__ views,
-                                                          const uint64_t* __restrict__ items, int64_t nitems,
-                                                          int* counter, int P, const double* __restrict__ x,
-                                                          const int64_t* __restrict__ x_off, BatchOut out) {
+// Persistent kernel: workgroups of G sub-groups take (system, polynomial)
+// items from a device counter in the order of `items` (decreasing cost) until
+// none is left; each item is evaluated at all P points.  When the row has at
+// most G chunks, every sub-group loads its chunk's records once and keeps
+// them in registers for all P points.  Every workgroup reaches the exit test
+// after every item, so the grid drains.
+template <int L, int SEG, int CPL, int G, int MODE>
+__global__ __launch_bounds__(G * kSub) void batch_rows_kernel(const SysView* __restrict__ views,
+                                                              const uint64_t* __restrict__ items, int64_t nitems,
+                                                              int* counter, int P, const double* __restrict__ x,
+                                                              const int64_t* __restrict__ x_off, BatchOut out) {
+  static_assert(4 * G <= kMaxWaves, "F partials region");
   extern __shared__ double lds[];
   __shared__ int64_t item_sh;
+  const int sg = sub_group();
+  const int lt = int(threadIdx.x) - sg * kSub;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
     __syncthreads();
@@ -729,20 +751,27 @@ __global__ __launch_bounds__(kSub) void batch_rows_kernel(const SysView* __restr
     }
     double* tab = lds;
     double* contrib = lds + tab_doubles(S, L);
-    double* fpart = contrib + size_t(S.max_slots) * 2 * L;
+    double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
     const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
+    const bool resident = ch1 - ch0 <= uint32_t(G);
+    ChunkLoads<L, SEG, CPL> cl;
+    if (resident) load_chunk<L, SEG, CPL, MODE>(S, ch0 + sg, ch0 + sg < ch1, lt, nullptr, cl);
+    const double* xs = x + x_off[s] * P;
+    C<L> x0 = table_first_x<L>(S, xs);
     for (int pt = 0; pt < P; ++pt) {
-      const double* xpt = x + x_off[s] * P + int64_t(pt) * 2 * L * n;
-      const C<L> x0 = table_first_x<L>(S, xpt);
-      ChunkLoads<L, SEG, CPL> cl;
-      load_chunk<L, SEG, CPL, MODE>(S, ch0, ch0 < ch1, int(threadIdx.x), nullptr, cl);
-      build_power_table<L, kSub>(S, xpt, tab, x0);
+      const double* xpt = xs + int64_t(pt) * 2 * L * n;
+      if (!resident) load_chunk<L, SEG, CPL, MODE>(S, ch0 + sg, ch0 + sg < ch1, lt, nullptr, cl);
+      // the previous point's write_row is done with the LDS before any
+      // thread passes this barrier
+      build_power_table<L, G * kSub>(S, xpt, tab, x0);
       __syncthreads();
+      // the next point's first table column is loaded while this one runs
+      if (pt + 1 < P) x0 = table_first_x<L>(S, xpt + 2 * L * n);
       C<L> acc[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-      process_chunks<L, SEG, CPL, 1, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
-      write_row<L, CPL, 1, MODE>(S, O, pt, p, acc, contrib, fpart);
+      process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
+      write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
     }
   }
 }

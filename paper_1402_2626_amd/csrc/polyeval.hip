@@ -43,6 +43,31 @@ pe_status fail(pe_status st, const std::string& msg) {
 // workgroup can hold four chunks at once), 68 KB for QD
 int default_seg(int L) { return L == 1 ? 8 : (L == 2 ? 8 : 4); }
 
+// Default segment length for a system: among the level's compiled lengths
+// (in order of preference), the first for which a monomial of the most
+// common size k fills all its lanes' segments exactly (then the monomial
+// sweeps run without branches); else the level's default.
+int default_seg_for(int L, const std::vector<int64_t>& mon_ptr) {
+  std::vector<int64_t> hist(kMaxMonomialVars + 1, 0);
+  for (size_t t = 0; t + 1 < mon_ptr.size(); ++t) {
+    const int64_t k = mon_ptr[t + 1] - mon_ptr[t];
+    if (k >= 1 && k <= kMaxMonomialVars) hist[size_t(k)] += k;
+  }
+  int kmode = 0;
+  for (int k = 1; k <= kMaxMonomialVars; ++k)
+    if (hist[size_t(k)] > hist[size_t(kmode)]) kmode = k;
+  if (kmode == 0) return default_seg(L);
+  static const int pref1[] = {8, 16}, pref2[] = {8, 6, 4}, pref4[] = {4, 2};
+  const int* pref = L == 1 ? pref1 : (L == 2 ? pref2 : pref4);
+  const int np = L == 1 ? 2 : (L == 2 ? 3 : 2);
+  for (int i = 0; i < np; ++i) {
+    const int seg = pref[i];
+    const int s = lanes_for(kmode, seg);
+    if (s <= kMaxWave && (kmode + s - 1) / s == seg) return seg;
+  }
+  return default_seg(L);
+}
+
 int default_slots(int L) { return L == 1 ? 2304 : (L == 2 ? 1152 : 1088); }
 
 int cpl_bucket(int ncols, int T) {
@@ -178,6 +203,7 @@ hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const 
   X(1, 16, 2)        \
   X(2, 4, 1)         \
   X(2, 4, 4)         \
+  X(2, 6, 1)         \
   X(2, 8, 1)         \
   X(2, 8, 2)         \
   X(4, 4, 1)         \
@@ -284,11 +310,11 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   return PE_OK;
 }
 
-// slot budget of a chunk: about 36 KB (D, DD; 70 KB with long segments) or
-// 68 KB (QD) of LDS
+// slot budget of a chunk: about 36 KB (D, DD; 70 KB with segments of 6 or
+// more) or 68 KB (QD) of LDS
 int slots_for(int L, int seg) {
   if (L == 4) return 1088;
-  const int bytes = (seg >= 8 && !(L == 1 && seg == 8)) ? 70 * 1024 : 36 * 1024;
+  const int bytes = (seg >= 6 && !(L == 1 && seg == 8)) ? 70 * 1024 : 36 * 1024;
   return std::max(kMaxMonomialVars + 1, bytes / (16 * L));
 }
 
@@ -445,7 +471,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
     return fail(PE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
   }
   // launch shape: from the plan cache if it knows this system, else the default
-  int seg = default_seg(level), G = 0;
+  int seg = default_seg_for(level, sys->in_mon_ptr), G = 0;
   pe_status ps = pack_and_upload(sys, seg, G, static_cast<hipStream_t>(stream));
   if (ps == PE_OK) {
     int cseg = 0, cG = 0;
@@ -492,7 +518,7 @@ pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_pe
   if (!sys) return fail(PE_EINVAL, "system is NULL");
   if (chunks_per_workgroup < 0 || chunks_per_workgroup > 4 || chunks_per_workgroup == 3 || segment < 0)
     return fail(PE_EINVAL, "invalid launch shape");
-  const int seg = segment ? segment : default_seg(sys->level);
+  const int seg = segment ? segment : default_seg_for(sys->level, sys->in_mon_ptr);
   if (!shape_compiled(sys->level, seg, chunks_per_workgroup ? chunks_per_workgroup : 1))
     return fail(PE_EUNSUPPORTED, "launch shape not compiled for this level");
   hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -680,6 +706,7 @@ struct pe_batch {
   int level = 0;
   int S = 0;
   int seg = 4;
+  int G = 1;  // chunks per workgroup of the persistent launch
   int cpl = 1;
   size_t lds = 0;
   int maxN = 0;
@@ -699,15 +726,15 @@ struct pe_batch {
 
 namespace {
 
-template <int L, int SEG, int CPL, int MODE>
+template <int L, int SEG, int CPL, int G, int MODE>
 hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const BatchOut& out, hipStream_t st) {
-  auto kern = batch_rows_kernel<L, SEG, CPL, MODE>;
+  auto kern = batch_rows_kernel<L, SEG, CPL, G, MODE>;
   if (b->lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds));
     if (e != hipSuccess) return e;
   }
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kSub, b->lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, b->lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -715,18 +742,18 @@ hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const Batch
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, b->nitems));
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kSub), b->lds, st, (const SysView*)b->d_views,
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), b->lds, st, (const SysView*)b->d_views,
                      (const uint64_t*)b->d_items, b->nitems, b->d_counter, P, x, (const int64_t*)b->d_offs, out);
   return hipGetLastError();
 }
 
-template <int L, int SEG>
+template <int L, int SEG, int G>
 hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode,
                               hipStream_t st) {
   switch (b->cpl * 4 + mode) {
 #define PE_CASE(CPL, MODE) \
   case CPL * 4 + MODE:     \
-    return launch_batch_t<L, SEG, CPL, MODE>(b, P, x, out, st);
+    return launch_batch_t<L, SEG, CPL, G, MODE>(b, P, x, out, st);
     PE_CASE(1, MODE_EVAL)
     PE_CASE(1, MODE_FONLY)
     PE_CASE(2, MODE_EVAL)
@@ -743,7 +770,7 @@ hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const B
 hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
   const int L = b->level, seg = b->seg;
 #define PE_X(L_, S_, G_) \
-  if (G_ == 1 && L == L_ && seg == S_) return dispatch_batch_seg<L_, S_>(b, P, x, out, mode, st);
+  if (G_ <= 2 && L == L_ && seg == S_ && b->G == G_) return dispatch_batch_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(b, P, x, out, mode, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
@@ -789,7 +816,8 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     const pe_system* y = systems[s];
     if (y->level != b->level || y->plan.seg != b->seg || y->device != b->device) {
       delete b;
-      return fail(PE_EINVAL, "batched systems must share level, launch shape and device");
+      return fail(PE_EINVAL, "batched systems must share level, segment length and device "
+                             "(pe_system_set_shape sets a common segment length)");
     }
     maxcols = std::max(maxcols, y->view.n);
     b->lds = std::max(b->lds, y->plan.lds1);
@@ -797,6 +825,22 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   }
   b->cpl = cpl_bucket(maxcols, kSub);
   const int L = b->level;
+  // two chunks per workgroup when compiled, when some row has two or more
+  // chunks, and when every system's table and two slot regions fit in LDS
+  {
+    int max_chunks = 0;
+    size_t lds2 = 0;
+    for (int s = 0; s < S; ++s) {
+      const pe_system* y = systems[s];
+      for (int p = 0; p < y->view.N; ++p)
+        max_chunks = std::max<int>(max_chunks, y->host.chunk_ptr[p + 1] - y->host.chunk_ptr[p]);
+      lds2 = std::max(lds2, lds_bytes<1>(y->view.n, y->view.tab_first, y->view.tab_last, y->view.max_slots, 2) * L);
+    }
+    if (shape_compiled(L, b->seg, 2) && max_chunks >= 2 && lds2 <= device_lds_limit()) {
+      b->G = 2;
+      b->lds = lds2;
+    }
+  }
   // packed layout per point
   b->x_off.assign(S + 1, 0);
   b->F_off.assign(S + 1, 0);
@@ -879,6 +923,15 @@ pe_status pe_batch_layout(const pe_batch* b, int64_t* x_off, int64_t* F_off, int
     if (F_off) F_off[s] = b->F_off[s];
     if (J_off) J_off[s] = b->J_off[s];
   }
+  return PE_OK;
+}
+
+pe_status pe_batch_info(const pe_batch* b, int64_t info[4]) {
+  if (!b || !info) return fail(PE_EINVAL, "NULL argument");
+  info[0] = b->S;
+  info[1] = b->level;
+  info[2] = b->seg;
+  info[3] = b->G;
   return PE_OK;
 }
 
@@ -984,7 +1037,7 @@ pe_status pe_autotune(pe_system* sys, int32_t P, void* stream) {
   const int best_seg0 = sys->plan.seg, best_G0 = sys->plan.G;
   int best_seg = best_seg0, best_G = best_G0;
   double best_us = 1e300;
-  for (int seg : {1, 2, 4, 8, 16})
+  for (int seg : {1, 2, 4, 6, 8, 16})
     for (int G : {1, 2, 4}) {
       if (!shape_compiled(L, seg, G)) continue;
       if (pe_system_set_shape(sys, seg, G, stream) != PE_OK) continue;

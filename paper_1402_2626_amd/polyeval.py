@@ -41,6 +41,7 @@ SIGNATURES = {
     "pe_batch_create": (_c_int, [ctypes.POINTER(_p), _c_int, _p, _p]),
     "pe_batch_destroy": (_c_int, [_p]),
     "pe_batch_layout": (_c_int, [_p, _p, _p, _p]),
+    "pe_batch_info": (_c_int, [_p, _p]),
     "pe_batch_eval": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_newton_workspace_bytes": (ctypes.c_size_t, [_p, _c_int]),
     "pe_newton_step": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
@@ -209,6 +210,11 @@ class Batch:
         jo = np.zeros(S + 1, np.int64)
         _check(_lib.pe_batch_layout(self._h, xo.ctypes.data, fo.ctypes.data, jo.ctypes.data), "pe_batch_layout")
         self.x_off, self.F_off, self.J_off = xo, fo, jo
+
+    def info(self) -> dict:
+        v = np.zeros(4, np.int64)
+        _check(_lib.pe_batch_info(self._h, v.ctypes.data), "pe_batch_info")
+        return {"systems": int(v[0]), "level": int(v[1]), "segment": int(v[2]), "chunks_per_workgroup": int(v[3])}
 
     def close(self):
         if getattr(self, "_h", None):

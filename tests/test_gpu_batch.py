@@ -48,6 +48,8 @@ def test_batch_uneven_matches_single_and_oracle(pe):
     xs = [synth.unit_circle_points(synth.rng_for((0, 300, i)), P, int(ns[i]), 2) for i in range(S_count)]
     xflat = U.to_device(_pack_points(B, xs, P))
     U.flush("batch: persistent launch")
+    G = B.info()["chunks_per_workgroup"]
+    assert B.info()["systems"] == S_count and G in (1, 2)
     F, J = B.eval(xflat, P)
     torch.cuda.synchronize()
     F, J = F.cpu().numpy(), J.cpu().numpy()
@@ -55,7 +57,7 @@ def test_batch_uneven_matches_single_and_oracle(pe):
         n = int(ns[i])
         Fi = _unpack(F, B.F_off, i, (P, 2, 2, n), P)
         Ji = _unpack(J, B.J_off, i, (P, 2, 2, n, n), P)
-        dev[i].set_shape(1)  # the batch evaluates one chunk at a time
+        dev[i].set_shape(G)  # the batch's chunks per workgroup
         F1, J1 = dev[i].eval(U.to_device(xs[i]))
         torch.cuda.synchronize()
         assert np.array_equal(F1.cpu().numpy(), Fi) and np.array_equal(J1.cpu().numpy(), Ji), i

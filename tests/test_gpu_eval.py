@@ -227,7 +227,7 @@ def test_shapes_and_autotune(pe, tmp_path):
     xd = U.to_device(x)
     tol = U.tolerance(sys_)
     seen = []
-    for seg in (4, 8):
+    for seg in (4, 6, 8):
         for G in (1, 2, 4):
             try:
                 S.set_shape(G, segment=seg)
@@ -261,3 +261,16 @@ def test_shapes_and_autotune(pe, tmp_path):
     finally:
         pe.set_plan_cache(None)
     S.close()
+
+
+@pytest.mark.gpu
+def test_default_segment_follows_monomial_size(pe):
+    """The default segment length is the first of the level's preferred
+    lengths that the most common monomial size fills exactly."""
+    cases = [(2, 16, 8), (2, 24, 6), (2, 12, 6), (2, 4, 4), (2, 20, 8), (4, 32, 4), (4, 6, 2), (1, 16, 8),
+             (1, 24, 8)]
+    for level, k, want in cases:
+        sys_ = synth.random_system(7, level, n_vars=64, n_polys=3, m=8, k=k, exp_lo=1, exp_hi=2)
+        S = pe.System.from_sparse(sys_)
+        assert S.info()["segment"] == want, (level, k)
+        S.close()
