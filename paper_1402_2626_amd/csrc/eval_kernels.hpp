@@ -513,7 +513,7 @@ __device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
 
 // Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
 // ch0 + sg, ch0 + sg + G, ...  `cl` holds the loads of the sub-group's first
-// chunk, issued by the caller; the loads of each next chunk are issued before
+// chunk, issued by the caller; the loads of each next chunk are issued around
 // the owner phase of the current one.  After the monomial phase of the last
 // chunk (before the barrier the fast wavefronts wait at anyway) every
 // wavefront stores its F partial, unless fpart is null.  F-only evaluation
@@ -542,8 +542,12 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
       cb[cc] = cl.cb[cc];
       ce[cc] = cl.ce[cc];
     }
-    if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    // D and DD issue the next chunk's loads before the owners add; QD, whose
+    // registers are already spilled to the accumulation registers, after
+    constexpr bool kEarly = L <= 2;
+    if (kEarly && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
     chunk_owners<L, CPL>(cb, ce, contrib, S.max_slots, acc);
+    if (!kEarly && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
     __syncthreads();
   }
 }

@@ -366,6 +366,84 @@ PE_HD C<2> c_mul<2>(const C<2>& a, const C<2>& b) {
   return C<2>{dd_dot2(a.re, b.re, a.im, b.im, -1.0), dd_dot2(a.re, b.im, a.im, b.re, 1.0)};
 }
 
+// Renormalise four components of any relative size (a fused sum may cancel
+// at order 0): a bottom-up pass of TwoSums, then a top-down compression.
+PE_HD R<4> renorm4(double c0, double c1, double c2, double c3) {
+  double x, e1, e2, e3, x0;
+  two_sum(c2, c3, x, e3);
+  two_sum(c1, x, x, e2);
+  two_sum(c0, x, x0, e1);
+  R<4> r;
+  double y;
+  fast_two_sum(x0, e1, r.x[0], y);
+  two_sum(y, e2, r.x[1], y);
+  two_sum(y, e3, r.x[2], r.x[3]);
+  return r;
+}
+
+// L = 4: each component is a*b + c*d of quad doubles, computed as one sum
+// of partial products grouped by order (the order of a_i b_j is i + j):
+// orders 0..2 by TwoProd with their sums taken exactly by TwoSum chains (the
+// errors of a chain belong to the next order), order 3 in plain arithmetic,
+// order 4 and beyond dropped, and one renormalisation at the end, instead
+// of two rounded products and a rounded sum.  Normwise error O(u^4)(|ab| +
+// |cd|), u = 2^-53.
+PE_HD R<4> qd_dot2(const R<4>& a, const R<4>& b, const R<4>& c, const R<4>& d) {
+  // order 0
+  double p0a, q0a, p0c, q0c, s0, e0;
+  two_prod(a.x[0], b.x[0], p0a, q0a);
+  two_prod(c.x[0], d.x[0], p0c, q0c);
+  two_sum(p0a, p0c, s0, e0);
+  // order 1: four products, their order-0 neighbours' errors and e0
+  double p1[4], q1[4];
+  two_prod(a.x[0], b.x[1], p1[0], q1[0]);
+  two_prod(a.x[1], b.x[0], p1[1], q1[1]);
+  two_prod(c.x[0], d.x[1], p1[2], q1[2]);
+  two_prod(c.x[1], d.x[0], p1[3], q1[3]);
+  double f[6], s1;
+  two_sum(p1[0], p1[1], s1, f[0]);
+  two_sum(s1, p1[2], s1, f[1]);
+  two_sum(s1, p1[3], s1, f[2]);
+  two_sum(s1, q0a, s1, f[3]);
+  two_sum(s1, q0c, s1, f[4]);
+  two_sum(s1, e0, s1, f[5]);
+  // order 2: six products, the order-1 products' errors and the chain's
+  // errors; the TwoSum errors of this chain are order-3 terms
+  double p2[6], q2[6];
+  two_prod(a.x[0], b.x[2], p2[0], q2[0]);
+  two_prod(a.x[1], b.x[1], p2[1], q2[1]);
+  two_prod(a.x[2], b.x[0], p2[2], q2[2]);
+  two_prod(c.x[0], d.x[2], p2[3], q2[3]);
+  two_prod(c.x[1], d.x[1], p2[4], q2[4]);
+  two_prod(c.x[2], d.x[0], p2[5], q2[5]);
+  double s2 = p2[0], g = 0.0, e;
+#pragma unroll
+  for (int i = 1; i < 6; ++i) {
+    two_sum(s2, p2[i], s2, e);
+    g += e;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    two_sum(s2, q1[i], s2, e);
+    g += e;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    two_sum(s2, f[i], s2, e);
+    g += e;
+  }
+  // order 3 (plain)
+  double o3 = PE_FMA(a.x[0], b.x[3], PE_FMA(a.x[1], b.x[2], PE_FMA(a.x[2], b.x[1], a.x[3] * b.x[0])));
+  o3 = PE_FMA(c.x[0], d.x[3], PE_FMA(c.x[1], d.x[2], PE_FMA(c.x[2], d.x[1], PE_FMA(c.x[3], d.x[0], o3))));
+  const double s3 = o3 + ((q2[0] + q2[1]) + (q2[2] + q2[3]) + (q2[4] + q2[5])) + g;
+  return renorm4(s0, s1, s2, s3);
+}
+
+template <>
+PE_HD C<4> c_mul<4>(const C<4>& a, const C<4>& b) {
+  return C<4>{qd_dot2(a.re, b.re, r_neg(a.im), b.im), qd_dot2(a.re, b.im, a.im, b.re)};
+}
+
 // ------------------------------------------------------------------ operation counts
 // FP64 operations per call of each primitive as written above (an FMA counts
 // once here; flop counts with FMA = 2 are derived from the FMA share).
@@ -388,12 +466,12 @@ struct OpCount<2> {
 };
 template <>
 struct OpCount<4> {
-  // r_mul: 6 two_prod (12) + o3 (1 mul + 3 fma) + 8 two_sum (48) + 8 adds +
-  // renorm4_ordered (5 fast_two_sum = 15) = 87, 9 FMAs
+  // qd_dot2: 12 two_prod (24) + 22 two_sum (132) + 15 error adds + o3 (1
+  // mul + 7 fma) + 8 adds + renorm4 (5 two_sum + 1 fast_two_sum = 33) =
+  // 220, 19 FMAs; c_mul = 2 qd_dot2 + 4 negations
   // r_add: 4 two_sum (24) + 3 two_sum (18) + 3 adds + renorm5 (6 two_sum +
-  // 1 fast_two_sum + 1 add = 40) + 4 negations folded = 85
-  // c_mul = 4 r_mul + 2 r_add (one of them r_sub: +4 negations)
-  static constexpr int cmul = 4 * 87 + 2 * 85 + 4, cmul_fma = 36;
+  // 1 fast_two_sum + 1 add = 40) = 85
+  static constexpr int cmul = 2 * 220 + 4, cmul_fma = 38;
   static constexpr int cadd = 170;
   // r_mul_d: 3 two_prod (6) + 1 mul + 3 two_sum (18) + 3 adds + 15 = 43, 3 FMAs
   static constexpr int cscal = 86, cscal_fma = 6;

@@ -9,10 +9,19 @@ Per complex level-L operation (flops):
 =========  ======  =======  =======
 op         L = 1   L = 2    L = 4
 =========  ======  =======  =======
-cmul       6       50       558
-cscal      2       16       92
-cadd       2       22       170
+cmul       6       50       478
+cscal      2       10       92
+cadd_J     2       16       170
+cadd_F     2       22       170
 =========  ======  =======  =======
+
+cmul: D one FMA and one product per component; DD the fused double-word
+two-product sum per component; QD the fused order-by-order sum of partial
+products per component.  cscal: the product of a partial derivative by its
+exponent (DD unnormalised, one product and two FMAs per component).  cadd_J:
+one slot added into a Jacobian column (DD: TwoSum on the high parts plus two
+plain additions per component, the compensated sum of the owners); cadd_F:
+one monomial value added into F.
 
 The algorithmic work of a monomial with k variables, l of them with exponent
 d >= 2, is the work of the reverse mode over its product of variables with
@@ -20,8 +29,8 @@ the coefficient and the common factor folded into the seed (Sec. 2.2-2.3):
 l products for the common factor, k-1 forward products, k-1 products for the
 partial derivatives and k for the backward products (the last one gives the
 monomial's value), i.e. l + 3k - 2 complex products; k scalings by the
-exponent; k + 1 additions into J and F.  A constant monomial (k = 0) costs one
-addition.  The table of powers costs n (emax - 2) products per point.  The
+exponent; k additions into J and one into F.  A constant monomial (k = 0)
+costs one addition.  The table of powers costs n (emax - 2) products per point.  The
 extra products of the library's lane decomposition (the butterfly across the
 lanes of a monomial) are not algorithmic and not counted, so a roofline
 fraction from these counts is a lower bound of the FP64 utilisation.
@@ -35,14 +44,14 @@ from __future__ import annotations
 import numpy as np
 
 FLOPS = {
-    1: dict(cmul=6, cscal=2, cadd=2),
-    2: dict(cmul=50, cscal=16, cadd=22),
-    4: dict(cmul=558, cscal=92, cadd=170),
+    1: dict(cmul=6, cscal=2, cadd_J=2, cadd_F=2),
+    2: dict(cmul=50, cscal=10, cadd_J=16, cadd_F=22),
+    4: dict(cmul=478, cscal=92, cadd_J=170, cadd_F=170),
 }
 
 
 def monomial_counts(sys_):
-    """(cmul, cscal, cadd) totals for one point."""
+    """(cmul, cscal, cadd_J, cadd_F) totals for one point."""
     k = np.diff(sys_.mon_ptr).astype(np.int64)
     hi = (sys_.exps >= 2).astype(np.int64)
     owner = np.repeat(np.arange(sys_.n_monomials), k)
@@ -53,14 +62,13 @@ def monomial_counts(sys_):
     emax = int(sys_.exps.max()) if sys_.nnz else 1
     cmul += sys_.n_vars * max(0, emax - 2)
     cscal = int(np.sum(k))
-    cadd = int(np.sum(k + 1))
-    return cmul, cscal, cadd
+    return cmul, cscal, int(np.sum(k)), int(sys_.n_monomials)
 
 
 def flops_per_point(sys_) -> float:
     f = FLOPS[sys_.level]
-    cmul, cscal, cadd = monomial_counts(sys_)
-    return float(cmul * f["cmul"] + cscal * f["cscal"] + cadd * f["cadd"])
+    cmul, cscal, cadd_j, cadd_f = monomial_counts(sys_)
+    return float(cmul * f["cmul"] + cscal * f["cscal"] + cadd_j * f["cadd_J"] + cadd_f * f["cadd_F"])
 
 
 def bytes_per_point(sys_, want_J: bool = True, chunks: int | None = None, R: int = 16) -> float:
