@@ -36,7 +36,7 @@ lanes of a monomial) are not algorithmic and not counted, so a roofline
 fraction from these counts is a lower bound of the FP64 utilisation.
 
 Bytes: the packed structure that one evaluation must read (8 bytes per
-occurrence record, 16L + 4 per monomial, 2 (n + R + 1) per chunk), x, and the
+occurrence record, 16L per monomial, 2 (n + 1) per chunk), x, and the
 F and J outputs (16L bytes per complex number).
 """
 from __future__ import annotations
@@ -71,12 +71,12 @@ def flops_per_point(sys_) -> float:
     return float(cmul * f["cmul"] + cscal * f["cscal"] + cadd_j * f["cadd_J"] + cadd_f * f["cadd_F"])
 
 
-def bytes_per_point(sys_, want_J: bool = True, chunks: int | None = None, R: int = 16) -> float:
+def bytes_per_point(sys_, want_J: bool = True, chunks: int | None = None) -> float:
     L = sys_.level
     c16 = 16 * L
-    b = 8.0 * sys_.nnz + (c16 + 4.0) * sys_.n_monomials
+    b = 8.0 * sys_.nnz + c16 * sys_.n_monomials
     if chunks is not None:
-        b += 2.0 * (sys_.n_vars + R + 1) * chunks
+        b += 2.0 * (sys_.n_vars + 1) * chunks
     b += c16 * sys_.n_vars + c16 * sys_.n_polys
     if want_J:
         b += c16 * sys_.n_polys * sys_.n_vars
