@@ -37,12 +37,14 @@ def describe(name):
     return (f"{name}: n={w['n']}, N={w['N']}, {w['m']} monomials/poly, k={w['k']}, "
             f"exps {{1..{w['exp_hi']}}}, {w['P']} point(s)")
 PEAK_FP64_TFLOPS = 78.6  # 256 CUs x 64 FP64 FMA lanes/clk x 2 flops x 2.4 GHz
+PEAK_HBM_GBS = 8000.0    # HBM3E
 
 # HBM bytes of the evaluation kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # passes (KiB per dispatch) scaled by what the same counters read for a plain
 # device copy of known size.  The figures hold for the kernel sources they
 # were taken with: `traffic` is null when the sources have changed since.
-COUNTERS = os.path.join(ROOT, "profiles", "eval_rows_dd_n256_counters.json")
+COUNTERS = {"dd_n256": os.path.join(ROOT, "profiles", "eval_rows_dd_n256_counters.json"),
+            "d_product_65024x1024": os.path.join(ROOT, "profiles", "eval_rows_d_product_counters.json")}
 KERNEL_SOURCES = ["eval_kernels.hpp", "mdarith.hpp", "layout.hpp", "polyeval.hip", "packer.cpp", "packer.hpp"]
 
 
@@ -58,9 +60,9 @@ def kernel_source_digest() -> str:
 def counter_traffic(workload: str):
     """HBM bytes per launch of the evaluation kernel, or None."""
     try:
-        with open(COUNTERS) as fh:
+        with open(COUNTERS[workload]) as fh:
             c = json.load(fh)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if c.get("workload") != workload or c.get("source_sha256") != kernel_source_digest():
         return None
@@ -105,8 +107,8 @@ def main():
                     help="time every compiled launch shape of the workload (one line each) and exit")
     ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512 "
-                         "and dd_batch4096 print the same kind of line for context")
+                    help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512, "
+                         "dd_batch4096 and d_product_65024x1024 print the same kind of line for context")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -129,6 +131,8 @@ def main():
         return bench_batch(args)
     if args.workload == "dd_adjoint_1024x512":
         return bench_adjoint(args)
+    if args.workload == "d_product_65024x1024":
+        return bench_product(args)
     sys_, x = synth.workload(args.workload)
     P = x.shape[0]
 
@@ -246,6 +250,41 @@ def bench_adjoint(args):
            "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
                         "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
            "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_product(args):
+    """The Table-1 shape in complex double: 65,024 one-monomial polynomials,
+    each the product of all 1,024 variables; F and the dense 65,024 x 1,024 J
+    at one point.  Bound by HBM (the J write dominates)."""
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    sys_, x = synth.product_workload()
+    S = pe.System.from_sparse(sys_)
+    xd = torch.from_numpy(x).cuda()
+    F = torch.empty((1, 2, 1, sys_.n_polys), dtype=torch.float64, device="cuda")
+    J = torch.empty((1, 2, 1, sys_.n_polys, sys_.n_vars), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K = min(args.steps, 50)
+    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, min(args.warmup, 5), st)
+    chunks = sys_.n_polys  # one chunk per polynomial
+    nbytes = W.bytes_per_point(sys_, want_J=True, chunks=chunks)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"metric": "monomial eval+grad/s (complex double, F + full J)",
+           "value": sys_.n_monomials * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K,
+           "warmup": min(args.warmup, 5), "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (double complex)", "data": "synthetic",
+           "config": {"workload": "d_product_65024x1024: 65,024 polynomials, each one monomial of all "
+                                  "n=1,024 variables (exponent 1), 1 point; dense J of 1.07 GB",
+                      "kernel_ms": ms, "algorithmic_bytes": nbytes,
+                      "flops": W.flops_per_point(sys_)},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": gbs / PEAK_HBM_GBS, "traffic": counter_traffic(args.workload)},
+           "cpu_baseline": None}
+    S.close()
     print(json.dumps(out), flush=True)
 
 

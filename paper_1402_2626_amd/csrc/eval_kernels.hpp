@@ -407,6 +407,9 @@ template <int L, int SEG, int CPL, int MODE>
 __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
                                                 const double* __restrict__ xpt, const double* tab,
                                                 double* contrib, C<L>& facc) {
+  // a wavefront whose lanes all lie past the chunk's last monomial has
+  // nothing to contribute (its records are all neutral)
+  if (__builtin_amdgcn_readfirstlane(lt & ~63) >= int(cl.cd.width)) return;
   if (int(cl.cd.seg) == SEG && tab_full(S))
     chunk_monomials_body<L, SEG, CPL, MODE, true>(S, cl, lt, xpt, tab, contrib, facc);
   else

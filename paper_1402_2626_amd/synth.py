@@ -304,6 +304,21 @@ WORKLOADS = {
     "dd_adjoint_1024x512": dict(level=2, n=512, N=1024, m=512, k=24, exp_hi=3, P=64),
 }
 
+# The shape of Table 1 (Section 2.2) in complex double: 65,024 polynomials, each
+# one monomial, the product of all 1,024 variables (exponent 1), unit-circle
+# coefficients and point; J is dense (65,024 x 1,024), so the evaluation is
+# bound by writing it.
+PRODUCT_WORKLOAD = dict(name="d_product_65024x1024", level=1, n=1024, N=65024, P=1)
+
+
+def product_workload(seed: int = 0):
+    """``(system, x[1, 2, 1, n])`` for the Table-1-shaped product workload;
+    the system uses stream ``seed``, the point stream ``(seed, 1)``."""
+    w = PRODUCT_WORKLOAD
+    sys_ = product_system(w["N"], w["n"], w["level"], seed=seed)
+    x = unit_circle_points(rng_for((seed, 1)), w["P"], w["n"], w["level"])
+    return sys_, x
+
 
 def workload(name: str, seed: int = 0, points: int | None = None):
     """Return ``(system, x[P, 2, L, n])`` for a named workload.

@@ -274,3 +274,48 @@ def test_default_segment_follows_monomial_size(pe):
         S = pe.System.from_sparse(sys_)
         assert S.info()["segment"] == want, (level, k)
         S.close()
+
+
+def _row_subsystem(sys_, rows):
+    """The polynomials `rows` of a system as a system of their own (same
+    variables), for oracle checks of sampled rows of a large system."""
+    from paper_1402_2626_amd.synth import PolySystem
+    mons = [list(range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1]))) for p in rows]
+    poly_ptr = np.cumsum([0] + [len(m) for m in mons]).astype(np.int64)
+    flat = [t for m in mons for t in m]
+    mon_ptr = np.cumsum([0] + [int(sys_.mon_ptr[t + 1] - sys_.mon_ptr[t]) for t in flat]).astype(np.int64)
+    occ = np.concatenate([np.arange(sys_.mon_ptr[t], sys_.mon_ptr[t + 1]) for t in flat]).astype(np.int64)
+    return PolySystem(level=sys_.level, n_vars=sys_.n_vars, poly_ptr=poly_ptr, mon_ptr=mon_ptr,
+                      var_idx=np.ascontiguousarray(sys_.var_idx[occ]), exps=np.ascontiguousarray(sys_.exps[occ]),
+                      coef=np.ascontiguousarray(sys_.coef[:, :, flat]), name=sys_.name + "_rows")
+
+
+def test_product_table1_shape(pe):
+    """The Table-1 shape in complex double (65,024 polynomials, each the
+    product of all 1,024 variables) at full size: three sampled rows against
+    the oracle, and on every row x_j dF/dx_j summed over j = 1024 F (Euler:
+    each polynomial is homogeneous of degree 1,024)."""
+    import torch
+    sys_, x = synth.product_workload()
+    S = pe.System.from_sparse(sys_)
+    assert S.info()["segment"] == 16
+    U.flush("product workload: one launch, J of 1.07 GB")
+    F, J = S.eval(U.to_device(x))
+    torch.cuda.synchronize()
+    S.close()
+    tol = U.tolerance(sys_)
+    rows = [0, 32511, sys_.n_polys - 1]
+    sub = _row_subsystem(sys_, rows)
+    Fs = F[:, :, :, rows].cpu().numpy()[0]
+    Js = J[:, :, :, rows, :].cpu().numpy()[0]
+    eF, eJ = U.max_errors_rows(sub, x[0], Fs, Js, range(len(rows)), parallel=True)
+    assert eF <= tol and eJ <= tol, (eF, eJ)
+    # Euler's identity on all rows, in complex128 on the device
+    xd = U.to_device(x)
+    xc = torch.complex(xd[0, 0, 0], xd[0, 1, 0])
+    Jc = torch.complex(J[0, 0, 0], J[0, 1, 0])
+    Fc = torch.complex(F[0, 0, 0], F[0, 1, 0])
+    lhs = (Jc * xc[None, :]).sum(dim=1)
+    err = ((lhs - 1024.0 * Fc).abs() / (1024.0 * Fc.abs())).max().item()
+    assert err <= tol, err
+    del F, J, Jc
