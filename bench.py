@@ -108,7 +108,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512, "
-                         "dd_batch4096 and d_product_65024x1024 print the same kind of line for context")
+                         "dd_batch4096, d_product_65024x1024, cyclic_d_n512 and cyclic_dd_n512 print the "
+                         "same kind of line for context")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,6 +134,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "d_product_65024x1024":
         return bench_product(args)
+    if args.workload in CYCLIC:
+        return bench_cyclic(args)
     sys_, x = synth.workload(args.workload)
     P = x.shape[0]
 
@@ -250,6 +253,42 @@ def bench_adjoint(args):
            "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
                         "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
            "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+# cyclic n-roots (eq. (5)); the paper's Table 5 times on its GPU are context
+CYCLIC = {"cyclic_d_n512": (1, 512, 46.43), "cyclic_dd_n512": (2, 512, 267.39)}
+
+
+def bench_cyclic(args):
+    """F and J of the cyclic n-roots system at one point on the unit circle."""
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    L, n, paper_ms = CYCLIC[args.workload]
+    sys_ = synth.cyclic_roots_system(n, L)
+    x = synth.unit_circle_points(synth.rng_for((0, 1)), 1, n, L)
+    S = pe.System.from_sparse(sys_)
+    xd = torch.from_numpy(x).cuda()
+    F = torch.empty((1, 2, L, n), dtype=torch.float64, device="cuda")
+    J = torch.empty((1, 2, L, n, n), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K = min(args.steps, 50)
+    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, min(args.warmup, 5), st)
+    flops = W.flops_per_point(sys_)
+    out = {"metric": "monomial eval+grad/s (complex %s, F + full J)" % LEVEL_NAME[L],
+           "value": sys_.n_monomials * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K,
+           "warmup": min(args.warmup, 5), "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (%s complex)" % LEVEL_NAME[L], "data": "synthetic",
+           "config": {"workload": "%s: cyclic n-roots, n=%d, %d monomials, 1 point" % (args.workload, n, sys_.n_monomials),
+                      "kernel_ms": ms, "segment": S.info()["segment"],
+                      "paper_table5_ms_context": paper_ms},
+           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
+           "cpu_baseline": None}
+    S.close()
     print(json.dumps(out), flush=True)
 
 

@@ -204,12 +204,25 @@ def cyclic_roots_system(n: int, level: int) -> PolySystem:
     """The cyclic n-roots system (eq. (5), Section 5.3): for i = 1..n-1 the sum
     over j of the products of i cyclically consecutive variables starting at
     x_j; the last polynomial is x_0 x_1 ... x_{n-1} - 1.  Coefficients are 1
-    except the constant -1.  n^2 - n + 2 monomials in total."""
-    polys = []
+    except the constant -1.  n^2 - n + 2 monomials in total; each monomial's
+    variables in increasing order."""
+    var_blocks, k_list = [], []
     for i in range(1, n):
-        polys.append([(1.0, sorted(((j + r) % n, 1) for r in range(i))) for j in range(n)])
-    polys.append([(1.0, [(j, 1) for j in range(n)]), (-1.0, [])])
-    return from_monomial_lists(level, n, polys, name=f"cyclic{n}")
+        idx = np.sort((np.arange(n)[:, None] + np.arange(i)[None, :]) % n, axis=1)
+        var_blocks.append(idx.reshape(-1))
+        k_list.append(np.full(n, i, np.int64))
+    var_blocks.append(np.arange(n))
+    k_list.append(np.array([n, 0], np.int64))
+    k = np.concatenate(k_list)
+    M = k.size
+    var_idx = np.concatenate(var_blocks).astype(np.int32)
+    coef = np.zeros((2, level, M))
+    coef[0, 0] = 1.0
+    coef[0, 0, -1] = -1.0
+    poly_ptr = np.concatenate([np.arange(0, n * (n - 1) + 1, n), [M]]).astype(np.int64)
+    return PolySystem(level=level, n_vars=n, poly_ptr=poly_ptr,
+                      mon_ptr=np.concatenate([[0], np.cumsum(k)]).astype(np.int64),
+                      var_idx=var_idx, exps=np.ones(var_idx.size, np.int32), coef=coef, name=f"cyclic{n}")
 
 
 def product_system(n_monomials: int, n_vars: int, level: int, seed=0) -> PolySystem:

@@ -319,3 +319,21 @@ def test_product_table1_shape(pe):
     err = ((lhs - 1024.0 * Fc).abs() / (1024.0 * Fc.abs())).max().item()
     assert err <= tol, err
     del F, J, Jc
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_cyclic_512_closed_forms(pe, L):
+    """Cyclic 512-roots (eq. (5)), the largest size of the paper's Table 5 for
+    D and DD, at x = 1: F_i = n for i < n, F_n = 0; J_{i,m} = i, last row 1;
+    every product and sum is exact."""
+    n = 512
+    sys_ = synth.cyclic_roots_system(n, L)
+    x = np.zeros((1, 2, L, n))
+    x[0, 0, 0] = 1.0
+    F, J = run_eval(pe, sys_, x)
+    want_F = np.full(n, float(n))
+    want_F[-1] = 0.0
+    assert np.array_equal(F[0, 0, 0], want_F) and np.all(F[0, 1] == 0) and np.all(F[0, 0, 1:] == 0)
+    want_J = np.repeat(np.arange(1, n + 1, dtype=float)[:, None], n, axis=1)
+    want_J[-1] = 1.0
+    assert np.array_equal(J[0, 0, 0], want_J) and np.all(J[0, 1] == 0) and np.all(J[0, 0, 1:] == 0)
