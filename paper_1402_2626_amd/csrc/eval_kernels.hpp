@@ -643,13 +643,15 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
 }
 
-// Adjoint: grid P * NG workgroups of 256 threads; group gi covers
-// polynomials [gi * gsize, min(N, (gi+1) * gsize)).  Writes partial rows
-// part[(pt * NG + gi)][2][L][n] (planar, plane stride n).
-template <int L, int SEG, int CPL>
-__global__ __launch_bounds__(kSub) void adjoint_rows_kernel(SysView S, const double* __restrict__ x, int64_t x_pt,
-                                                            const double* __restrict__ v, int64_t v_pt, int NG,
-                                                            int gsize, double* __restrict__ part) {
+// Adjoint: grid P * NG workgroups of G * 256 threads; group gi covers
+// polynomials [gi * gsize, min(N, (gi+1) * gsize)), its chunks taken G at a
+// time.  The G sub-groups' column sums are added in sub-group order, and the
+// result is written as the partial row part[(pt * NG + gi)][2][L][n]
+// (planar, plane stride n).
+template <int L, int SEG, int CPL, int G>
+__global__ __launch_bounds__(G * kSub) void adjoint_rows_kernel(SysView S, const double* __restrict__ x, int64_t x_pt,
+                                                                const double* __restrict__ v, int64_t v_pt, int NG,
+                                                                int gsize, double* __restrict__ part) {
   extern __shared__ double lds[];
   const int pt = blockIdx.x / NG;
   const int gi = blockIdx.x - pt * NG;
@@ -660,19 +662,40 @@ __global__ __launch_bounds__(kSub) void adjoint_rows_kernel(SysView S, const dou
   const int p0 = gi * gsize;
   const int p1 = min(S.N, p0 + gsize);
   const uint32_t ch0 = S.chunk_ptr[p0], ch1 = S.chunk_ptr[p1];
+  const int sg = sub_group();
+  const int lt = int(threadIdx.x) - sg * kSub;
   ChunkLoads<L, SEG, CPL> cl;
   const C<L> x0 = table_first_x<L>(S, xpt);
-  load_chunk<L, SEG, CPL, MODE_ADJ>(S, ch0, ch0 < ch1, int(threadIdx.x), vpt, cl);
-  build_power_table<L, kSub>(S, xpt, tab, x0);
+  load_chunk<L, SEG, CPL, MODE_ADJ>(S, ch0 + sg, ch0 + sg < ch1, lt, vpt, cl);
+  build_power_table<L, G * kSub>(S, xpt, tab, x0);
   __syncthreads();
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, 1, MODE_ADJ>(S, ch0, ch1, xpt, vpt, tab, contrib, acc, nullptr, cl);
+  process_chunks<L, SEG, CPL, G, MODE_ADJ>(S, ch0, ch1, xpt, vpt, tab, contrib, acc, nullptr, cl);
+  if (G > 1) {
+    // the slot regions are free (process_chunks ends with a barrier)
+    if (sg > 0) {
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const int c = lt + cc * kSub;
+        if (c < S.n) lds_st(contrib + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
+      }
+    }
+    __syncthreads();
+    if (sg > 0) return;
+    for (int o = 1; o < G; ++o) {
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const int c = lt + cc * kSub;
+        if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(contrib + size_t(o - 1) * (2 * L) * S.n, S.n, c));
+      }
+    }
+  }
   double* out = part + size_t(pt * NG + gi) * 2 * L * S.n;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    const int c = threadIdx.x + cc * kSub;
+    const int c = lt + cc * kSub;
     if (c < S.n) store_planar(out, S.n, c, acc[cc]);
   }
 }

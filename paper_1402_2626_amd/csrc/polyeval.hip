@@ -142,17 +142,17 @@ hipError_t launch_rows_t(const pe_system* sys, int P, const double* x, const Out
   return hipGetLastError();
 }
 
-template <int L, int SEG, int CPL>
+template <int L, int SEG, int CPL, int G>
 hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
-  auto kern = adjoint_rows_kernel<L, SEG, CPL>;
-  const size_t lds = sys->plan.lds1;
+  auto kern = adjoint_rows_kernel<L, SEG, CPL, G>;
+  const size_t lds = G > 1 ? sys->plan.lds : sys->plan.lds1;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
   const int n = sys->view.n;
-  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(kSub), lds, st, sys->view, x,
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(G * kSub), lds, st, sys->view, x,
                      int64_t(2) * L * n, v, int64_t(2) * L * sys->view.N, NG, gsize, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -181,14 +181,23 @@ hipError_t dispatch_rows_lsg(const pe_system* sys, int P, const double* x, const
   return hipErrorInvalidValue;
 }
 
-template <int L, int SEG>
+// the adjoint runs with the evaluation plan's chunks per workgroup when that
+// is 2 (at most 512 columns), else with one chunk at a time
+template <int L, int SEG, int G>
 hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                             double* part, double* g, hipStream_t st) {
+  if (G == 2) {
+    switch (sys->plan.cpl) {
+      case 1: return launch_adj_t<L, SEG, 1, 2>(sys, P, x, v, NG, gsize, part, g, st);
+      case 2: return launch_adj_t<L, SEG, 2, 2>(sys, P, x, v, NG, gsize, part, g, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (sys->plan.cpl) {
-    case 1: return launch_adj_t<L, SEG, 1>(sys, P, x, v, NG, gsize, part, g, st);
-    case 2: return launch_adj_t<L, SEG, 2>(sys, P, x, v, NG, gsize, part, g, st);
-    case 4: return launch_adj_t<L, SEG, 4>(sys, P, x, v, NG, gsize, part, g, st);
-    case 8: return launch_adj_t<L, SEG, 8>(sys, P, x, v, NG, gsize, part, g, st);
+    case 1: return launch_adj_t<L, SEG, 1, 1>(sys, P, x, v, NG, gsize, part, g, st);
+    case 2: return launch_adj_t<L, SEG, 2, 1>(sys, P, x, v, NG, gsize, part, g, st);
+    case 4: return launch_adj_t<L, SEG, 4, 1>(sys, P, x, v, NG, gsize, part, g, st);
+    case 8: return launch_adj_t<L, SEG, 8, 1>(sys, P, x, v, NG, gsize, part, g, st);
   }
   return hipErrorInvalidValue;
 }
@@ -204,6 +213,7 @@ hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const 
   X(2, 4, 1)         \
   X(2, 4, 4)         \
   X(2, 6, 1)         \
+  X(2, 6, 2)         \
   X(2, 8, 1)         \
   X(2, 8, 2)         \
   X(4, 4, 1)         \
@@ -230,8 +240,9 @@ hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const Out
 hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
   const int L = sys->level, seg = sys->plan.seg;
+  const int G = sys->plan.G == 2 ? 2 : 1;
 #define PE_X(L_, S_, G_) \
-  if (G_ == 1 && L == L_ && seg == S_) return dispatch_adj_seg<L_, S_>(sys, P, x, v, NG, gsize, part, g, st);
+  if (G_ <= 2 && L == L_ && seg == S_ && G == G_) return dispatch_adj_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(sys, P, x, v, NG, gsize, part, g, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
