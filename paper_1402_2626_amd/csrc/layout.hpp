@@ -4,8 +4,9 @@
 // A polynomial's monomials are cut into CHUNKS.  A chunk is processed by one
 // workgroup in one pass: every monomial of the chunk gets a group of `s`
 // consecutive lanes (s a power of two, at most one wavefront), lane q of the
-// group handles a contiguous segment of at most `seg` of the monomial's
-// variables, and each partial derivative is written to its own LDS SLOT.
+// group handles the SEGMENT of the monomial's occurrences q, q + s, q + 2s, ...
+// (at most `seg` of them; occurrences in variable order), and each partial
+// derivative is written to its own LDS SLOT.
 // Slots are numbered so that the contributions to one Jacobian column are
 // contiguous: column c owns slots colptr[c] .. colptr[c+1]-1.  This
 // owner-computes order is fixed at load time, so results are bitwise

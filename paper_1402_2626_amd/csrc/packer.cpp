@@ -247,17 +247,21 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
         occ_sorted.clear();
         for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o]});
         std::sort(occ_sorted.begin(), occ_sorted.end(), [](const Occ& x, const Occ& y) { return x.var < y.var; });
+        // lane q of the group takes occurrences q, q + s, q + 2s, ... (in
+        // variable order): a wavefront's gathers and slot stores at one step
+        // then touch neighbouring variables when a monomial's variables are
+        // runs of consecutive indices, instead of addresses a segment apart
         const int base = k / s, extra = k % s;
         for (int q = 0; q < s; ++q) {
           const int len = base + (q < extra ? 1 : 0);
-          const int r0 = q * base + std::min(q, extra);
           const int lane = g * s + q;
           for (int ii = 0; ii < len; ++ii) {
-            const Occ& oc = occ_sorted[size_t(r0 + ii)];
+            const int r = q + ii * s;
+            const Occ& oc = occ_sorted[size_t(r)];
             OccRec& rec = out.occ[rec0 + size_t(ii) * cd.width + size_t(lane)];
             rec.var = uint16_t(oc.var);
             rec.exp = uint16_t(oc.exp);
-            rec.slot = uint16_t(slot_of[size_t(g)][size_t(r0 + ii)]);
+            rec.slot = uint16_t(slot_of[size_t(g)][size_t(r)]);
           }
         }
         // packed monomial: coefficient and metadata

@@ -101,7 +101,7 @@ def test_pack_invariants(lib, seg):
             for g in range(count):
                 k = int(P["mmeta"][mb + g])
                 assert lanes_for(max(k, 1), seg) <= sl and k <= sl * segc
-                occs = []
+                occs = [None] * k
                 base, extra = k // sl, k % sl
                 for q in range(sl):
                     ln = base + (1 if q < extra else 0)
@@ -111,9 +111,10 @@ def test_pack_invariants(lib, seg):
                             # neutral padding: the constant-1 column, exponent 1, the dummy slot
                             assert (var, ex, slot) == (n, 1, nslots)
                             continue
-                        occs.append((int(var), int(ex)))
+                        occs[q + i * sl] = (int(var), int(ex))  # lane q holds occurrences q, q + s, ...
                         assert col_of_slot[slot] == var
                         slots.append(int(slot))
+                assert None not in occs
                 assert [v for v, _ in occs] == sorted(v for v, _ in occs)  # canonical order
                 got.append(tuple(occs))
                 seen_mon.add(mb + g)
