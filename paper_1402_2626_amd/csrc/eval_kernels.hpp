@@ -327,7 +327,9 @@ __device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* t
 // FAST: the chunk's segments have exactly SEG records and the power table
 // holds every power the common factors need, so the sweeps have no branches
 // at all and the compiler can interleave the independent product chains.
-template <int L, int SEG, int CPL, int MODE, bool FAST>
+// POW false (FAST only): every exponent of the system is 1, so there is no
+// common factor and no exponent to multiply by.
+template <int L, int SEG, int CPL, int MODE, bool FAST, bool POW = true>
 __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
                                                      const double* __restrict__ xpt, const double* tab,
                                                      double* contrib, C<L>& facc) {
@@ -356,7 +358,8 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
   for (int i = 0; i < SEG; ++i) {
     if (FAST || i < segc) {
       const int v = cl.rec[i].var, d = cl.rec[i].exp;
-      if (full) {
+      if (!POW) {
+      } else if (full) {
         cf = c_mul(cf, cf_factor_full<L>(S, tab, v, d));
       } else if (d >= 2) {
         cf = c_mul(cf, d == 2 ? xv[i] : power_of<L>(S, tab, v, d - 1, xv[i]));
@@ -392,13 +395,13 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
     if (FAST || i < segc) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      lds_st(contrib, ms, cl.rec[i].slot, scale_by_exponent(gi, double(cl.rec[i].exp)));
+      lds_st(contrib, ms, cl.rec[i].slot, POW ? scale_by_exponent(gi, double(cl.rec[i].exp)) : gi);
     }
   }
   if (FAST || segc >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    lds_st(contrib, ms, cl.rec[0].slot, scale_by_exponent(g0, double(cl.rec[0].exp)));
+    lds_st(contrib, ms, cl.rec[0].slot, POW ? scale_by_exponent(g0, double(cl.rec[0].exp)) : g0);
   }
   if (MODE == MODE_EVAL && active && q == 0) facc = c_add(facc, Sx);
 }
@@ -410,9 +413,12 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoa
   // a wavefront whose lanes all lie past the chunk's last monomial has
   // nothing to contribute (its records are all neutral)
   if (__builtin_amdgcn_readfirstlane(lt & ~63) >= int(cl.cd.width)) return;
-  if (int(cl.cd.seg) == SEG && tab_full(S))
-    chunk_monomials_body<L, SEG, CPL, MODE, true>(S, cl, lt, xpt, tab, contrib, facc);
-  else
+  if (int(cl.cd.seg) == SEG && tab_full(S)) {
+    if (S.emax >= 2)
+      chunk_monomials_body<L, SEG, CPL, MODE, true, true>(S, cl, lt, xpt, tab, contrib, facc);
+    else
+      chunk_monomials_body<L, SEG, CPL, MODE, true, false>(S, cl, lt, xpt, tab, contrib, facc);
+  } else
     chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
 }
 
