@@ -731,8 +731,8 @@ struct BatchOut {
   int newton;
 };
 
-__global__ void reset_counter_kernel(int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+__global__ void reset_counter_kernel(int* counter, int count) {
+  if (blockIdx.x == 0 && int(threadIdx.x) < count) counter[threadIdx.x] = 0;
 }
 
 // Persistent kernel: workgroups of G sub-groups take (system, polynomial)

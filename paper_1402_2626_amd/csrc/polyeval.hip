@@ -712,14 +712,26 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
 
 // ------------------------------------------------------------------ batches
 
+// One persistent launch of a batch: the (system, polynomial) items of one
+// class of systems, in decreasing cost.
+struct BatchClass {
+  int G = 1;  // chunks per workgroup
+  int cpl = 1;
+  size_t lds = 0;
+  int64_t nitems = 0;
+  uint64_t* d_items = nullptr;
+};
+
 struct pe_batch {
   int device = 0;
   int level = 0;
   int S = 0;
   int seg = 4;
-  int G = 1;  // chunks per workgroup of the persistent launch
-  int cpl = 1;
-  size_t lds = 0;
+  // class 0: systems with a row of two or more chunks (two chunks per
+  // workgroup when compiled and fitting); class 1: the others, one chunk per
+  // workgroup with the LDS of the small systems only, so that several
+  // workgroups share a CU
+  BatchClass cls[2];
   int maxN = 0;
   std::vector<const pe_system*> systems;
   std::vector<int64_t> x_off, F_off, J_off;  // per point, doubles, [S+1]
@@ -727,44 +739,41 @@ struct pe_batch {
   int64_t w_total = 0, r_total = 0, y_total = 0;  // per point, doubles
   int64_t nitems = 0;
   SysView* d_views = nullptr;
-  uint64_t* d_items = nullptr;
   int64_t* d_offs = nullptr;  // x_off | F_off | J_off | W offsets, each [S+1]
   BatchNewtonDesc* d_ndesc = nullptr;
   int* d_order = nullptr;
-  int* d_counter = nullptr;
-  int grid = 0;
+  int* d_counter = nullptr;  // [2], one per class
 };
 
 namespace {
 
 template <int L, int SEG, int CPL, int G, int MODE>
-hipError_t launch_batch_t(const pe_batch* b, int P, const double* x, const BatchOut& out, hipStream_t st) {
+hipError_t launch_batch_t(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, hipStream_t st) {
+  const BatchClass& K = b->cls[c];
   auto kern = batch_rows_kernel<L, SEG, CPL, G, MODE>;
-  if (b->lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds));
+  if (K.lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(K.lds));
     if (e != hipSuccess) return e;
   }
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, b->lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, K.lds);
   if (e != hipSuccess) return e;
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, b->nitems));
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), b->lds, st, (const SysView*)b->d_views,
-                     (const uint64_t*)b->d_items, b->nitems, b->d_counter, P, x, (const int64_t*)b->d_offs, out);
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, K.nitems));
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), K.lds, st, (const SysView*)b->d_views,
+                     (const uint64_t*)K.d_items, K.nitems, b->d_counter + c, P, x, (const int64_t*)b->d_offs, out);
   return hipGetLastError();
 }
 
 template <int L, int SEG, int G>
-hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode,
+hipError_t dispatch_batch_seg(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, int mode,
                               hipStream_t st) {
-  switch (b->cpl * 4 + mode) {
+  switch (b->cls[c].cpl * 4 + mode) {
 #define PE_CASE(CPL, MODE) \
   case CPL * 4 + MODE:     \
-    return launch_batch_t<L, SEG, CPL, G, MODE>(b, P, x, out, st);
+    return launch_batch_t<L, SEG, CPL, G, MODE>(b, c, P, x, out, st);
     PE_CASE(1, MODE_EVAL)
     PE_CASE(1, MODE_FONLY)
     PE_CASE(2, MODE_EVAL)
@@ -778,18 +787,30 @@ hipError_t dispatch_batch_seg(const pe_batch* b, int P, const double* x, const B
   return hipErrorInvalidValue;
 }
 
-hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
-  const int L = b->level, seg = b->seg;
+hipError_t dispatch_batch_class(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, int mode,
+                                hipStream_t st) {
+  const int L = b->level, seg = b->seg, G = b->cls[c].G;
 #define PE_X(L_, S_, G_) \
-  if (G_ <= 2 && L == L_ && seg == S_ && b->G == G_) return dispatch_batch_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(b, P, x, out, mode, st);
+  if (G_ <= 2 && L == L_ && seg == S_ && G == G_) return dispatch_batch_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(b, c, P, x, out, mode, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
 }
 
+// reset both queue counters (a kernel, so the launch can be captured), then
+// one persistent launch per non-empty class
+hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter, 2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int c = 0; c < 2; ++c)
+    if (b->cls[c].nitems > 0 && (e = dispatch_batch_class(b, c, P, x, out, mode, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
 void batch_free(pe_batch* b) {
-  for (void* p : {(void*)b->d_views, (void*)b->d_items, (void*)b->d_offs, (void*)b->d_ndesc, (void*)b->d_order,
-                  (void*)b->d_counter})
+  for (void* p : {(void*)b->d_views, (void*)b->cls[0].d_items, (void*)b->cls[1].d_items, (void*)b->d_offs,
+                  (void*)b->d_ndesc, (void*)b->d_order, (void*)b->d_counter})
     if (p) (void)hipFree(p);
 }
 
@@ -822,7 +843,6 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   b->level = systems[0]->level;
   b->seg = systems[0]->plan.seg;
   b->device = systems[0]->device;
-  int maxcols = 1;
   for (int s = 0; s < S; ++s) {
     const pe_system* y = systems[s];
     if (y->level != b->level || y->plan.seg != b->seg || y->device != b->device) {
@@ -830,27 +850,31 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
       return fail(PE_EINVAL, "batched systems must share level, segment length and device "
                              "(pe_system_set_shape sets a common segment length)");
     }
-    maxcols = std::max(maxcols, y->view.n);
-    b->lds = std::max(b->lds, y->plan.lds1);
     b->maxN = std::max(b->maxN, y->view.N);
   }
-  b->cpl = cpl_bucket(maxcols, kSub);
   const int L = b->level;
-  // two chunks per workgroup when compiled, when some row has two or more
-  // chunks, and when every system's table and two slot regions fit in LDS
-  {
-    int max_chunks = 0;
-    size_t lds2 = 0;
-    for (int s = 0; s < S; ++s) {
-      const pe_system* y = systems[s];
-      for (int p = 0; p < y->view.N; ++p)
-        max_chunks = std::max<int>(max_chunks, y->host.chunk_ptr[p + 1] - y->host.chunk_ptr[p]);
+  // classes: systems with a row of two or more chunks (class 0), the others
+  // (class 1); per class the columns, the one-chunk LDS and, for class 0,
+  // two chunks per workgroup when compiled and when every system's table and
+  // two slot regions fit in LDS
+  std::vector<int> cls_of(S, 1);
+  int maxcols[2] = {1, 1};
+  size_t lds2 = 0;
+  for (int s = 0; s < S; ++s) {
+    const pe_system* y = systems[s];
+    int mc = 0;
+    for (int p = 0; p < y->view.N; ++p) mc = std::max<int>(mc, y->host.chunk_ptr[p + 1] - y->host.chunk_ptr[p]);
+    const int c = mc >= 2 ? 0 : 1;
+    cls_of[s] = c;
+    maxcols[c] = std::max(maxcols[c], y->view.n);
+    b->cls[c].lds = std::max(b->cls[c].lds, y->plan.lds1);
+    if (c == 0)
       lds2 = std::max(lds2, lds_bytes<1>(y->view.n, y->view.tab_first, y->view.tab_last, y->view.max_slots, 2) * L);
-    }
-    if (shape_compiled(L, b->seg, 2) && max_chunks >= 2 && lds2 <= device_lds_limit()) {
-      b->G = 2;
-      b->lds = lds2;
-    }
+  }
+  for (int c = 0; c < 2; ++c) b->cls[c].cpl = cpl_bucket(maxcols[c], kSub);
+  if (shape_compiled(L, b->seg, 2) && lds2 > 0 && lds2 <= device_lds_limit()) {
+    b->cls[0].G = 2;
+    b->cls[0].lds = lds2;
   }
   // packed layout per point
   b->x_off.assign(S + 1, 0);
@@ -878,16 +902,21 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   b->w_total = w_off[S];
   b->r_total = ro;
   b->y_total = yo;
-  // work items in decreasing cost (longest processing time first)
-  std::vector<std::pair<int64_t, uint64_t>> items;
-  for (int s = 0; s < S; ++s) {
-    const Packed& H = systems[s]->host;
-    for (int p = 0; p < H.N; ++p) items.push_back({H.poly_cost[p], (uint64_t(s) << 32) | uint64_t(p)});
+  // work items of each class in decreasing cost (longest processing time
+  // first)
+  std::vector<uint64_t> it[2];
+  for (int c = 0; c < 2; ++c) {
+    std::vector<std::pair<int64_t, uint64_t>> items;
+    for (int s = 0; s < S; ++s) {
+      if (cls_of[s] != c) continue;
+      const Packed& H = systems[s]->host;
+      for (int p = 0; p < H.N; ++p) items.push_back({H.poly_cost[p], (uint64_t(s) << 32) | uint64_t(p)});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& q) { return a.first > q.first; });
+    for (const auto& pr : items) it[c].push_back(pr.second);
+    b->cls[c].nitems = int64_t(it[c].size());
   }
-  std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
-  std::vector<uint64_t> it(items.size());
-  for (size_t i = 0; i < items.size(); ++i) it[i] = items[i].second;
-  b->nitems = int64_t(it.size());
+  b->nitems = b->cls[0].nitems + b->cls[1].nitems;
   std::vector<SysView> views(S);
   for (int s = 0; s < S; ++s) views[s] = systems[s]->view;
   std::vector<int64_t> offs;
@@ -902,14 +931,15 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   });
   hipStream_t hs = static_cast<hipStream_t>(stream);
   pe_status e = PE_OK;
-  if ((e = upload_raw(views, &b->d_views, hs)) != PE_OK || (e = upload_raw(it, &b->d_items, hs)) != PE_OK ||
+  if ((e = upload_raw(views, &b->d_views, hs)) != PE_OK || (e = upload_raw(it[0], &b->cls[0].d_items, hs)) != PE_OK ||
+      (e = upload_raw(it[1], &b->cls[1].d_items, hs)) != PE_OK ||
       (e = upload_raw(offs, &b->d_offs, hs)) != PE_OK || (e = upload_raw(b->ndesc, &b->d_ndesc, hs)) != PE_OK ||
       (e = upload_raw(order, &b->d_order, hs)) != PE_OK) {
     batch_free(b);
     delete b;
     return e;
   }
-  hipError_t he = hipMalloc(reinterpret_cast<void**>(&b->d_counter), sizeof(int));
+  hipError_t he = hipMalloc(reinterpret_cast<void**>(&b->d_counter), 2 * sizeof(int));
   if (he == hipSuccess) he = hipStreamSynchronize(hs);
   if (he != hipSuccess) {
     batch_free(b);
@@ -942,7 +972,7 @@ pe_status pe_batch_info(const pe_batch* b, int64_t info[4]) {
   info[0] = b->S;
   info[1] = b->level;
   info[2] = b->seg;
-  info[3] = b->G;
+  info[3] = b->cls[0].nitems > 0 ? b->cls[0].G : b->cls[1].G;
   return PE_OK;
 }
 
