@@ -329,7 +329,10 @@ __device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* t
 // at all and the compiler can interleave the independent product chains.
 // POW false (FAST only): every exponent of the system is 1, so there is no
 // common factor and no exponent to multiply by.
-template <int L, int SEG, int CPL, int MODE, bool FAST, bool POW = true>
+// GX (with POW false only): there is no LDS table and x is gathered from
+// global memory (neighbouring lanes take neighbouring occurrences, so the
+// gathers of a monomial whose variables are consecutive coalesce).
+template <int L, int SEG, int CPL, int MODE, bool FAST, bool POW = true, bool GX = false>
 __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
                                                      const double* __restrict__ xpt, const double* tab,
                                                      double* contrib, C<L>& facc) {
@@ -347,10 +350,21 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
   // every gather of the segment before any arithmetic, so that the LDS
   // latencies overlap
   C<L> xv[SEG];
+  if (GX) {
+    // padding records name column n, the constant 1
 #pragma unroll
-  for (int i = 0; i < SEG; ++i)
-    xv[i] = (FAST || i < segc) ? (FAST ? lds_ld<L>(tab, tab_cols(S), cl.rec[i].var) : load_x<L>(S, xpt, tab, cl.rec[i].var))
-                               : c_one<L>();
+    for (int i = 0; i < SEG; ++i) {
+      const int v = cl.rec[i].var;
+      const C<L> t = load_planar<L>(xpt, S.n, v < S.n ? v : 0);
+      xv[i] = v < S.n ? t : c_one<L>();
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SEG; ++i)
+      xv[i] = (FAST || i < segc)
+                  ? (FAST ? lds_ld<L>(tab, tab_cols(S), cl.rec[i].var) : load_x<L>(S, xpt, tab, cl.rec[i].var))
+                  : c_one<L>();
+  }
 
   C<L> pre[SEG > 1 ? SEG - 1 : 1];
   C<L> A = c_one<L>();
@@ -418,7 +432,9 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoa
       chunk_monomials_body<L, SEG, CPL, MODE, true, true>(S, cl, lt, xpt, tab, contrib, facc);
     else
       chunk_monomials_body<L, SEG, CPL, MODE, true, false>(S, cl, lt, xpt, tab, contrib, facc);
-  } else
+  } else if (L <= 2 && int(cl.cd.seg) == SEG && S.emax == 1 && tab_entries(S) == 0)
+    chunk_monomials_body<L, SEG, CPL, MODE, true, false, true>(S, cl, lt, xpt, tab, contrib, facc);
+  else
     chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
 }
 

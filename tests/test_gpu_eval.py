@@ -263,6 +263,36 @@ def test_shapes_and_autotune(pe, tmp_path):
     S.close()
 
 
+@pytest.mark.parametrize("L", [1, 2])
+def test_products_without_power_table(pe, L):
+    """Exponent-1 systems whose rows use each variable about once: x is
+    gathered from global memory and the LDS holds only the slots.  Full rows
+    against the oracle with full segments (k = 64), ragged segments (k = 50)
+    and, at a segment of 4, rows of two chunks."""
+    import torch
+    cases = [(512, 6, 8, 64, 0), (512, 6, 6, 50, 0)]
+    if L == 2:
+        cases.append((2000, 3, 30, 64, 4))
+    for n, N, m, k, seg in cases:
+        sys_ = synth.random_system((33, n, k), L, n_vars=n, n_polys=N, m=m, k=k, exp_lo=1, exp_hi=1)
+        x = synth.unit_circle_points(synth.rng_for((34, n, k)), 1, n, L)
+        S = pe.System.from_sparse(sys_)
+        if seg:
+            S.set_shape(0, seg)
+        info = S.info()
+        # slots (at most m k + 1 per chunk) and the F partials only: a table
+        # of x would add (n + 1) 16 L bytes
+        assert info["lds_bytes"] <= (m * k + 1 + 16) * 16 * L, info
+        U.flush(f"products without table: L={L} n={n} k={k} segment={info['segment']}")
+        F, J = S.eval(U.to_device(x))
+        torch.cuda.synchronize()
+        S.close()
+        F, J = F.cpu().numpy(), J.cpu().numpy()
+        eF, eJ = U.max_errors_rows(sys_, x[0], F[0], J[0], range(N), parallel=True)
+        tol = U.tolerance(sys_)
+        assert eF <= tol and eJ <= tol, (n, k, eF, eJ, tol)
+
+
 @pytest.mark.gpu
 def test_default_segment_follows_monomial_size(pe):
     """The default segment length is the first of the level's preferred
