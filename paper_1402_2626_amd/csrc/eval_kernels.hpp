@@ -329,8 +329,8 @@ __device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* t
 // at all and the compiler can interleave the independent product chains.
 // POW false (FAST only): every exponent of the system is 1, so there is no
 // common factor and no exponent to multiply by.
-// GX (with POW false only): there is no LDS table and x is gathered from
-// global memory (neighbouring lanes take neighbouring occurrences, so the
+// GX (double precision, with POW false only): there is no LDS table and x is
+// gathered from global memory (neighbouring lanes take neighbouring occurrences, so the
 // gathers of a monomial whose variables are consecutive coalesce).
 template <int L, int SEG, int CPL, int MODE, bool FAST, bool POW = true, bool GX = false>
 __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
@@ -432,10 +432,15 @@ __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoa
       chunk_monomials_body<L, SEG, CPL, MODE, true, true>(S, cl, lt, xpt, tab, contrib, facc);
     else
       chunk_monomials_body<L, SEG, CPL, MODE, true, false>(S, cl, lt, xpt, tab, contrib, facc);
-  } else if (L <= 2 && int(cl.cd.seg) == SEG && S.emax == 1 && tab_entries(S) == 0)
-    chunk_monomials_body<L, SEG, CPL, MODE, true, false, true>(S, cl, lt, xpt, tab, contrib, facc);
-  else
-    chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
+    return;
+  }
+  if constexpr (L == 1) {
+    if (int(cl.cd.seg) == SEG && S.emax == 1 && tab_entries(S) == 0) {
+      chunk_monomials_body<L, SEG, CPL, MODE, true, false, true>(S, cl, lt, xpt, tab, contrib, facc);
+      return;
+    }
+  }
+  chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
 }
 
 // Double-double column sum: compensated summation (Ogita, Rump and Oishi's

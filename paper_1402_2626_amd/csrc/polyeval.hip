@@ -279,13 +279,13 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, G) * L; };
   // table of powers in LDS, in order of preference: for D and DD x itself
   // first (its gathers are frequent next to cheap arithmetic) and then as
-  // many powers as fit; for QD only powers >= 2.  When every exponent is 1
-  // and a row has on average at most one occurrence per variable (products of
-  // many variables), building the table would cost as many loads as the
-  // gathers it serves: x is gathered from global memory instead and the LDS
-  // holds the slots only.
+  // many powers as fit; for QD only powers >= 2.  In double precision, when
+  // every exponent is 1 and a row has on average at most one occurrence per
+  // variable (products of many variables), building the table would cost as
+  // many loads as the gathers it serves: x is gathered from global memory
+  // instead and the LDS holds the slots only.
   std::vector<std::pair<int, int>> tables;
-  if (L <= 2 && H.emax == 1 && H.nnz <= int64_t(H.N) * H.n) tables.push_back({2, 0});
+  if (L == 1 && H.emax == 1 && H.nnz <= int64_t(H.N) * H.n) tables.push_back({2, 0});
   const int emax1 = std::max(H.emax - 1, 1);
   if (L <= 2)
     for (int tl = emax1; tl >= 1; --tl) tables.push_back({1, tl});
