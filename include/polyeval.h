@@ -145,10 +145,13 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
 
 /* ------------------------------------------------------------------ batches
  * A batch evaluates S independent systems of the same level, each at the
- * same number of points, in one persistent launch whose work items
- * (system, point, polynomial) are taken from a device queue in decreasing
- * order of cost.  The systems must share the level and the segment length
- * (pe_system_set_shape; PE_EINVAL otherwise) and outlive the batch. */
+ * same number of points, in persistent launches whose work items
+ * (system, polynomial; all points) are taken from a device queue in
+ * decreasing order of cost.  Systems with a row of two or more chunks form
+ * one launch, the others a second one sized for their LDS; both are queued
+ * on the caller's stream behind one counter-reset kernel.  The systems must
+ * share the level and the segment length (pe_system_set_shape; PE_EINVAL
+ * otherwise) and outlive the batch. */
 pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream);
 pe_status pe_batch_destroy(pe_batch* batch);
 
@@ -159,12 +162,13 @@ pe_status pe_batch_destroy(pe_batch* batch);
  * (J). */
 pe_status pe_batch_layout(const pe_batch* batch, int64_t* x_off, int64_t* F_off, int64_t* J_off);
 
-/* Shape of the persistent launch: info[0] = S, [1] = level, [2] = segment
- * length, [3] = chunks per workgroup (2 when compiled for the level and
- * segment, when some row has two or more chunks and every system fits in
- * LDS with two slot regions, else 1).  A row evaluated in the batch gives
- * bitwise the same F and J as pe_eval on its system with that many chunks
- * per workgroup. */
+/* Shape of the persistent launches: info[0] = S, [1] = level, [2] = segment
+ * length, [3] = chunks per workgroup of the launch over the systems with
+ * multi-chunk rows (2 when compiled for the level and segment and when each
+ * of those systems fits in LDS with two slot regions, else 1; 1 when no
+ * system has such a row).  A row evaluated in the batch gives bitwise the
+ * same F and J as pe_eval on its system with that many chunks per workgroup
+ * (a row of one chunk gives the same bits with any). */
 pe_status pe_batch_info(const pe_batch* batch, int64_t info[4]);
 
 /* Evaluate every system of the batch at points_per_system points each.
