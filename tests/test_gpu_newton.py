@@ -86,6 +86,43 @@ def test_newton_dd_n256_planted(pe):
     S.close()
 
 
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_newton_chandrasekhar_from_one(pe, L):
+    """Chandrasekhar's H-equation (Sec. 5.2, c = 33/64, n = 24, coefficients
+    rounded to double) from H = 1, where the paper reports quadratic
+    convergence: every device iterate follows the oracle's Gauss-Newton
+    iterate (Householder QR at 600 bits) from the same start, the error to the
+    oracle's converged solution decays quadratically to the level's floor, and
+    the solution is real with every H_i > 1."""
+    import torch
+    n = 24
+    sys_ = synth.chandrasekhar_system(n, L)
+    x0 = np.zeros((2, L, n))
+    x0[0, 0, :] = 1.0
+    Xo = O.point_from_limbs(x0)
+    Xs = Xo
+    for _ in range(8):  # 8 oracle steps: error below 1e-170
+        Xs, _ = O.gauss_newton_step_mp(sys_, Xs, prec=600)
+    S = pe.System.from_sparse(sys_)
+    xd = U.to_device(x0[None])
+    u = 2.0 ** (-53 * L)
+    errs = []
+    for it in range(7 if L == 4 else 6):
+        S.newton_step(xd)
+        torch.cuda.synchronize()
+        Xo, _ = O.gauss_newton_step_mp(sys_, Xo, prec=600)
+        xg = xd.cpu().numpy()[0]
+        errs.append(_dist(xg, Xs, L))
+        dev = _dist(xg, Xo, L)
+        assert dev <= 1e4 * u + 1e-3 * errs[-1], (it, dev, errs)
+    for a, b in zip(errs, errs[1:]):
+        assert b <= 1e4 * a * a + 1e4 * u, errs
+    assert errs[-1] <= 1e4 * u, errs
+    xg = xd.cpu().numpy()[0]
+    assert np.all(xg[0, 0] > 1.0) and np.all(np.abs(xg[1, 0]) <= 1e4 * u), xg[:, 0]
+    S.close()
+
 def test_newton_overdetermined(pe):
     """N = 16 > n = 9, consistent (planted): converges to x*."""
     import torch
