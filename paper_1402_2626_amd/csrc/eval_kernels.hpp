@@ -52,6 +52,8 @@ struct SysView {
   const OccRec* occ;
   const double* mcoef;  // [M][2L]
   const uint16_t* colptr;
+  const uint32_t* row_order;  // [N] rows in decreasing cost (workgroup b of a
+                              // point takes row row_order[b]), or null: row b
 };
 
 // output addressing: element (pt, c, l, row, col) of J is at
@@ -638,8 +640,9 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 
 // ------------------------------------------------------------------ kernels
 
-// grid: P * N workgroups of G * 256 threads, block (pt, p) = (blockIdx.x / N,
-// blockIdx.x % N)
+// grid: P * N workgroups of G * 256 threads; block (pt, b) = (blockIdx.x / N,
+// blockIdx.x % N) evaluates row p = row_order[b] (p = b without an order) at
+// point pt
 template <int L, int SEG, int CPL, int G, int MODE>
 __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
                                                              int64_t x_pt) {
@@ -647,7 +650,8 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   static_assert(4 * G <= kMaxWaves, "F partials region");
   extern __shared__ double lds[];
   const int pt = blockIdx.x / S.N;
-  const int p = blockIdx.x - pt * S.N;
+  const int b = blockIdx.x - pt * S.N;
+  const int p = S.row_order ? int(S.row_order[b]) : b;
   const double* xpt = x + pt * x_pt;
   double* tab = lds;
   double* contrib = lds + tab_doubles(S, L);

@@ -384,6 +384,24 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
       (e = upload(sys, P.occ, V.occ, hs)) != PE_OK || (e = upload(sys, P.mcoef, V.mcoef, hs)) != PE_OK ||
       (e = upload(sys, P.colptr, V.colptr, hs)) != PE_OK)
     return e;
+  // rows of very uneven cost (cyclic n-roots: row i holds monomials of i
+  // variables) are started in decreasing cost, so that the longest rows do
+  // not wait for a CU behind the short ones; even rows keep the identity
+  // (no extra load before the first descriptors)
+  {
+    int64_t mx = 0, sum = 0;
+    for (int64_t c : P.poly_cost) {
+      mx = std::max(mx, c);
+      sum += c;
+    }
+    if (P.N >= 2 && 2 * mx * P.N >= 3 * sum) {
+      std::vector<uint32_t> order(size_t(P.N));
+      for (int p = 0; p < P.N; ++p) order[size_t(p)] = uint32_t(p);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](uint32_t a, uint32_t c) { return P.poly_cost[a] > P.poly_cost[c]; });
+      if ((e = upload(sys, order, V.row_order, hs)) != PE_OK) return e;
+    }
+  }
   PE_HIP(hipStreamSynchronize(hs));
   // the device copies are authoritative; keep only what batches and tuning need
   sys->host.occ.clear();

@@ -295,6 +295,33 @@ def test_products_without_power_table(pe, L):
         assert eF <= tol and eJ <= tol, (n, k, eF, eJ, tol)
 
 
+@pytest.mark.parametrize("L", [1, 2])
+def test_uneven_rows(pe, L):
+    """Rows of very different cost (row p holds 1 + 12p monomials of six
+    variables, the longest spanning two chunks) are started in decreasing
+    cost; every row must still land in its own place of F and J.  All rows
+    against the oracle, at two points."""
+    import torch
+    rng = synth.rng_for((41, L))
+    n, N = 48, 40
+    polys = []
+    for p in range(N):
+        mons = []
+        for _ in range(1 + 12 * p):
+            vs = np.sort(rng.choice(n, size=6, replace=False))
+            ds = rng.integers(1, 4, size=6)
+            c = complex(*rng.normal(size=2))
+            mons.append((c, [(int(v), int(d)) for v, d in zip(vs, ds)]))
+        polys.append(mons)
+    sys_ = synth.from_monomial_lists(L, n, polys)
+    x = synth.unit_circle_points(synth.rng_for((42, L)), 2, n, L)
+    F, J = run_eval(pe, sys_, x)
+    tol = U.tolerance(sys_)
+    for pt in range(2):
+        eF, eJ = U.max_errors_rows(sys_, x[pt], F[pt], J[pt], range(N), parallel=True)
+        assert eF <= tol and eJ <= tol, (pt, eF, eJ, tol)
+
+
 @pytest.mark.gpu
 def test_default_segment_follows_monomial_size(pe):
     """The default segment length is the first of the level's preferred
