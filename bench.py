@@ -112,8 +112,8 @@ def main():
                          "same kind of line for context")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rows of F and J shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rows of F and J would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     from paper_1402_2626_amd import synth
