@@ -545,8 +545,9 @@ __device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
 
 // Process chunks [ch0, ch1) into the accumulators; sub-group sg takes chunks
 // ch0 + sg, ch0 + sg + G, ...  `cl` holds the loads of the sub-group's first
-// chunk, issued by the caller; the loads of each next chunk are issued around
-// the owner phase of the current one.  After the monomial phase of the last
+// chunk, issued by the caller; the loads of each next chunk are issued after
+// the wavefront's monomial phase (DD), before the owner phase (D) or after it
+// (QD).  After the monomial phase of the last
 // chunk (before the barrier the fast wavefronts wait at anyway) every
 // wavefront stores its F partial, unless fpart is null.  F-only evaluation
 // writes no slots and needs no barriers here.
@@ -567,19 +568,23 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
       if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
       continue;
     }
-    __syncthreads();
     int cb[CPL], ce[CPL];
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       cb[cc] = cl.cb[cc];
       ce[cc] = cl.ce[cc];
     }
-    // D and DD issue the next chunk's loads before the owners add; QD, whose
-    // registers are already spilled to the accumulation registers, after
-    constexpr bool kEarly = L <= 2;
-    if (kEarly && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    // the next chunk's loads: DD issues them as soon as the wavefront's
+    // monomial phase is done (a wavefront that waits at the barrier has them
+    // in flight meanwhile), D after the barrier (its four-chunk kernels have
+    // no registers to spare across it), QD, whose registers are already
+    // spilled to the accumulation registers, after the owners add
+    constexpr int kWhen = L == 2 ? 0 : (L == 1 ? 1 : 2);
+    if (kWhen == 0 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    __syncthreads();
+    if (kWhen == 1 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
     chunk_owners<L, CPL>(cb, ce, contrib, S.max_slots, acc);
-    if (!kEarly && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    if (kWhen == 2 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
     __syncthreads();
   }
 }
