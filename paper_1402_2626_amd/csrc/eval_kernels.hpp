@@ -761,10 +761,6 @@ struct BatchOut {
   int newton;
 };
 
-__global__ void reset_counter_kernel(int* counter, int count) {
-  if (blockIdx.x == 0 && int(threadIdx.x) < count) counter[threadIdx.x] = 0;
-}
-
 // Persistent kernel: workgroups of G sub-groups take (system, polynomial)
 // items from a device counter in the order of `items` (decreasing cost) until
 // none is left; each item is evaluated at all P points.  When the row has at

@@ -1,0 +1,27 @@
+// Instances of the kernel launchers of launch.hpp for one level and one kind,
+// chosen at compile time: PE_LEVEL (1, 2 or 4) and PE_KIND (0 rows, 1 adjoint,
+// 2 batch, 3 Gauss-Newton).  The build compiles this file once per pair.
+#define PE_LAUNCH_DEFINITIONS
+#include "launch.hpp"
+
+#if !defined(PE_LEVEL) || !defined(PE_KIND)
+#error "compile with -DPE_LEVEL=<1|2|4> -DPE_KIND=<0..3>"
+#endif
+
+namespace pe {
+
+#if PE_KIND == 0
+template hipError_t launch_rows<PE_LEVEL>(const EvalShape&, int, const double*, const OutView&, int, hipStream_t);
+#elif PE_KIND == 1
+template hipError_t launch_adjoint<PE_LEVEL>(const EvalShape&, int, const double*, const double*, int, int, double*,
+                                             double*, hipStream_t);
+#elif PE_KIND == 2
+template hipError_t launch_batch<PE_LEVEL>(const BatchShape&, int, const double*, const BatchOut&, int, hipStream_t);
+#elif PE_KIND == 3
+template hipError_t launch_mgs<PE_LEVEL>(int, int, int, double*, int64_t, double*, int64_t, double*, int64_t, double*,
+                                         double*, hipStream_t);
+template hipError_t launch_mgs_batch<PE_LEVEL>(int, int, int, const BatchNewtonDesc*, const int*, double*, double*,
+                                               double*, double*, double*, hipStream_t);
+#endif
+
+}  // namespace pe

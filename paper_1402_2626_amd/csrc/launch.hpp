@@ -1,0 +1,245 @@
+// Host-side launchers of the device kernels.  Each launcher is a template
+// over the level L; its instances for one (level, kind) are compiled in their
+// own translation unit (instances.hip built with PE_LEVEL and PE_KIND), so the
+// library builds in parallel.  polyeval.hip only sees the declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "eval_kernels.hpp"
+#include "newton_kernels.hpp"
+
+namespace pe {
+
+// The compiled launch shapes (level, segment length, chunks per workgroup).
+// A workgroup of G chunks has G * 256 threads; G > 1 is compiled for up to
+// 512 columns only.
+#define PE_SHAPES(X) \
+  X(1, 8, 1)         \
+  X(1, 8, 4)         \
+  X(1, 16, 1)        \
+  X(1, 16, 2)        \
+  X(2, 4, 1)         \
+  X(2, 4, 4)         \
+  X(2, 6, 1)         \
+  X(2, 6, 2)         \
+  X(2, 8, 1)         \
+  X(2, 8, 2)         \
+  X(4, 4, 1)         \
+  X(4, 2, 1)
+
+inline bool shape_compiled(int L, int seg, int G) {
+#define PE_X(L_, S_, G_) \
+  if (L == L_ && seg == S_ && G == G_) return true;
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return false;
+}
+
+// what a launch over one system needs to know about its plan
+struct EvalShape {
+  SysView view;
+  int seg = 4, G = 1, cpl = 1;
+  size_t lds = 0;   // dynamic LDS of a workgroup of G chunks
+  size_t lds1 = 0;  // dynamic LDS of a one-chunk workgroup
+};
+
+// one persistent launch over the items of a batch class
+struct BatchShape {
+  int seg = 4, G = 1, cpl = 1;
+  size_t lds = 0;
+  int64_t nitems = 0;
+  const uint64_t* items = nullptr;
+  const SysView* views = nullptr;
+  const int64_t* x_off = nullptr;
+  int* counter = nullptr;
+};
+
+template <int L>
+hipError_t launch_rows(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st);
+template <int L>
+hipError_t launch_adjoint(const EvalShape& sh, int P, const double* x, const double* v, int NG, int gsize,
+                          double* part, double* g, hipStream_t st);
+template <int L>
+hipError_t launch_batch(const BatchShape& b, int P, const double* x, const BatchOut& out, int mode,
+                        hipStream_t st);
+template <int L>
+hipError_t launch_mgs(int P, int N, int n, double* W, int64_t w_pt, double* R, int64_t r_pt, double* Y,
+                      int64_t y_pt, double* x, double* resid, hipStream_t st);
+template <int L>
+hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc, const int* order, double* W,
+                            double* R, double* Y, double* x, double* resid, hipStream_t st);
+
+#ifdef PE_LAUNCH_DEFINITIONS
+
+template <typename K>
+hipError_t allow_lds(K kern, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
+template <int L, int SEG, int CPL, int G, int MODE>
+hipError_t launch_rows_t(const EvalShape& sh, int P, const double* x, const OutView& O, hipStream_t st) {
+  auto kern = eval_rows_kernel<L, SEG, CPL, G, MODE>;
+  hipError_t e = allow_lds(kern, sh.lds);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = int64_t(P) * sh.view.N;
+  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), sh.lds, st, sh.view, O, x,
+                     int64_t(2) * L * sh.view.n);
+  return hipGetLastError();
+}
+
+template <int L, int SEG, int G>
+hipError_t rows_lsg(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st) {
+  const int cpl = sh.cpl;
+  if (mode == MODE_EVAL) {
+    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_EVAL>(sh, P, x, O, st);
+    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_EVAL>(sh, P, x, O, st);
+    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_EVAL>(sh, P, x, O, st);
+    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_EVAL>(sh, P, x, O, st);
+  } else {
+    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_FONLY>(sh, P, x, O, st);
+    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_FONLY>(sh, P, x, O, st);
+    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_FONLY>(sh, P, x, O, st);
+    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_FONLY>(sh, P, x, O, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+hipError_t launch_rows(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st) {
+#define PE_X(L_, S_, G_) \
+  if constexpr (L == L_) \
+    if (sh.seg == S_ && sh.G == G_) return rows_lsg<L_, S_, G_>(sh, P, x, O, mode, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return hipErrorInvalidValue;
+}
+
+template <int L, int SEG, int CPL, int G>
+hipError_t launch_adj_t(const EvalShape& sh, int P, const double* x, const double* v, int NG, int gsize,
+                        double* part, double* g, hipStream_t st) {
+  auto kern = adjoint_rows_kernel<L, SEG, CPL, G>;
+  const size_t lds = G > 1 ? sh.lds : sh.lds1;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int n = sh.view.n;
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(G * kSub), lds, st, sh.view, x,
+                     int64_t(2) * L * n, v, int64_t(2) * L * sh.view.N, NG, gsize, part);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = int64_t(P) * n;
+  hipLaunchKernelGGL(adjoint_reduce_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, n, NG, P,
+                     (const double*)part, g);
+  return hipGetLastError();
+}
+
+// the adjoint runs with the evaluation plan's chunks per workgroup when that
+// is 2 (at most 512 columns), else with one chunk at a time
+template <int L, int SEG, int G>
+hipError_t adj_lsg(const EvalShape& sh, int P, const double* x, const double* v, int NG, int gsize,
+                   double* part, double* g, hipStream_t st) {
+  if constexpr (G == 2) {
+    switch (sh.cpl) {
+      case 1: return launch_adj_t<L, SEG, 1, 2>(sh, P, x, v, NG, gsize, part, g, st);
+      case 2: return launch_adj_t<L, SEG, 2, 2>(sh, P, x, v, NG, gsize, part, g, st);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    switch (sh.cpl) {
+      case 1: return launch_adj_t<L, SEG, 1, 1>(sh, P, x, v, NG, gsize, part, g, st);
+      case 2: return launch_adj_t<L, SEG, 2, 1>(sh, P, x, v, NG, gsize, part, g, st);
+      case 4: return launch_adj_t<L, SEG, 4, 1>(sh, P, x, v, NG, gsize, part, g, st);
+      case 8: return launch_adj_t<L, SEG, 8, 1>(sh, P, x, v, NG, gsize, part, g, st);
+    }
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int L>
+hipError_t launch_adjoint(const EvalShape& sh, int P, const double* x, const double* v, int NG, int gsize,
+                          double* part, double* g, hipStream_t st) {
+  const int G = sh.G == 2 ? 2 : 1;
+#define PE_X(L_, S_, G_) \
+  if constexpr (L == L_ && G_ <= 2) \
+    if (sh.seg == S_ && G == G_) return adj_lsg<L_, S_, G_>(sh, P, x, v, NG, gsize, part, g, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return hipErrorInvalidValue;
+}
+
+template <int L, int SEG, int CPL, int G, int MODE>
+hipError_t launch_batch_t(const BatchShape& K, int P, const double* x, const BatchOut& out, hipStream_t st) {
+  auto kern = batch_rows_kernel<L, SEG, CPL, G, MODE>;
+  hipError_t e = allow_lds(kern, K.lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, K.lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, K.nitems));
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), K.lds, st, K.views, K.items, K.nitems, K.counter,
+                     P, x, K.x_off, out);
+  return hipGetLastError();
+}
+
+template <int L, int SEG, int G>
+hipError_t batch_lsg(const BatchShape& K, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
+  switch (K.cpl * 4 + mode) {
+#define PE_CASE(CPL, MODE) \
+  case CPL * 4 + MODE:     \
+    return launch_batch_t<L, SEG, CPL, G, MODE>(K, P, x, out, st);
+    PE_CASE(1, MODE_EVAL)
+    PE_CASE(1, MODE_FONLY)
+    PE_CASE(2, MODE_EVAL)
+    PE_CASE(2, MODE_FONLY)
+    PE_CASE(4, MODE_EVAL)
+    PE_CASE(4, MODE_FONLY)
+    PE_CASE(8, MODE_EVAL)
+    PE_CASE(8, MODE_FONLY)
+#undef PE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+hipError_t launch_batch(const BatchShape& K, int P, const double* x, const BatchOut& out, int mode,
+                        hipStream_t st) {
+#define PE_X(L_, S_, G_) \
+  if constexpr (L == L_ && G_ <= 2) \
+    if (K.seg == S_ && K.G == G_) return batch_lsg<L_, S_, G_>(K, P, x, out, mode, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+hipError_t launch_mgs(int P, int N, int n, double* W, int64_t w_pt, double* R, int64_t r_pt, double* Y,
+                      int64_t y_pt, double* x, double* resid, hipStream_t st) {
+  auto kern = mgs_solve_kernel<L, kMgsThreads>;
+  const size_t lds = mgs_lds_bytes<L>(N);
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(unsigned(P)), dim3(kMgsThreads), lds, st, N, n, W, w_pt, R, r_pt, Y, y_pt, x,
+                     int64_t(2) * L * n, resid);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc, const int* order, double* W,
+                            double* R, double* Y, double* x, double* resid, hipStream_t st) {
+  auto kern = mgs_solve_batch_kernel<L, kMgsThreads>;
+  const size_t lds = mgs_lds_bytes<L>(maxN);
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(S) * P)), dim3(kMgsThreads), lds, st, desc, order, P, W, R, Y, x,
+                     resid);
+  return hipGetLastError();
+}
+
+#endif  // PE_LAUNCH_DEFINITIONS
+
+}  // namespace pe

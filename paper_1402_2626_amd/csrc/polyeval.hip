@@ -14,8 +14,7 @@
 #include <vector>
 
 #include "polyeval.h"
-#include "eval_kernels.hpp"
-#include "newton_kernels.hpp"
+#include "launch.hpp"
 #include "packer.hpp"
 
 using namespace pe;
@@ -128,123 +127,36 @@ struct pe_system {
 
 namespace {
 
-template <int L, int SEG, int CPL, int G, int MODE>
-hipError_t launch_rows_t(const pe_system* sys, int P, const double* x, const OutView& O, hipStream_t st) {
-  auto kern = eval_rows_kernel<L, SEG, CPL, G, MODE>;
-  const size_t lds = sys->plan.lds;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-  }
-  const int64_t blocks = int64_t(P) * sys->view.N;
-  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), lds, st, sys->view, O, x,
-                     int64_t(2) * L * sys->view.n);
-  return hipGetLastError();
-}
-
-template <int L, int SEG, int CPL, int G>
-hipError_t launch_adj_t(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
-                        double* part, double* g, hipStream_t st) {
-  auto kern = adjoint_rows_kernel<L, SEG, CPL, G>;
-  const size_t lds = G > 1 ? sys->plan.lds : sys->plan.lds1;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-  }
-  const int n = sys->view.n;
-  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(G * kSub), lds, st, sys->view, x,
-                     int64_t(2) * L * n, v, int64_t(2) * L * sys->view.N, NG, gsize, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t tot = int64_t(P) * n;
-  hipLaunchKernelGGL(adjoint_reduce_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, n, NG, P,
-                     (const double*)part, g);
-  return hipGetLastError();
-}
-
-// dispatch over (CPL, MODE) for one compiled (L, SEG, G)
-template <int L, int SEG, int G>
-hipError_t dispatch_rows_lsg(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
-                             hipStream_t st) {
-  const int cpl = sys->plan.cpl;
-  if (mode == MODE_EVAL) {
-    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_EVAL>(sys, P, x, O, st);
-    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_EVAL>(sys, P, x, O, st);
-    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_EVAL>(sys, P, x, O, st);
-    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_EVAL>(sys, P, x, O, st);
-  } else {
-    if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_FONLY>(sys, P, x, O, st);
-    if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_FONLY>(sys, P, x, O, st);
-    if (G == 1 && cpl == 4) return launch_rows_t<L, SEG, 4, 1, MODE_FONLY>(sys, P, x, O, st);
-    if (G == 1 && cpl == 8) return launch_rows_t<L, SEG, 8, 1, MODE_FONLY>(sys, P, x, O, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-// the adjoint runs with the evaluation plan's chunks per workgroup when that
-// is 2 (at most 512 columns), else with one chunk at a time
-template <int L, int SEG, int G>
-hipError_t dispatch_adj_seg(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
-                            double* part, double* g, hipStream_t st) {
-  if (G == 2) {
-    switch (sys->plan.cpl) {
-      case 1: return launch_adj_t<L, SEG, 1, 2>(sys, P, x, v, NG, gsize, part, g, st);
-      case 2: return launch_adj_t<L, SEG, 2, 2>(sys, P, x, v, NG, gsize, part, g, st);
-    }
-    return hipErrorInvalidValue;
-  }
-  switch (sys->plan.cpl) {
-    case 1: return launch_adj_t<L, SEG, 1, 1>(sys, P, x, v, NG, gsize, part, g, st);
-    case 2: return launch_adj_t<L, SEG, 2, 1>(sys, P, x, v, NG, gsize, part, g, st);
-    case 4: return launch_adj_t<L, SEG, 4, 1>(sys, P, x, v, NG, gsize, part, g, st);
-    case 8: return launch_adj_t<L, SEG, 8, 1>(sys, P, x, v, NG, gsize, part, g, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-// The compiled launch shapes (level, segment length, chunks per workgroup).
-// A workgroup of G chunks has G * 256 threads; G > 1 is compiled for up to
-// 512 columns only.
-#define PE_SHAPES(X) \
-  X(1, 8, 1)         \
-  X(1, 8, 4)         \
-  X(1, 16, 1)        \
-  X(1, 16, 2)        \
-  X(2, 4, 1)         \
-  X(2, 4, 4)         \
-  X(2, 6, 1)         \
-  X(2, 6, 2)         \
-  X(2, 8, 1)         \
-  X(2, 8, 2)         \
-  X(4, 4, 1)         \
-  X(4, 2, 1)
-
-bool shape_compiled(int L, int seg, int G) {
-#define PE_X(L_, S_, G_) \
-  if (L == L_ && seg == S_ && G == G_) return true;
-  PE_SHAPES(PE_X)
-#undef PE_X
-  return false;
+EvalShape eval_shape(const pe_system* sys) {
+  EvalShape sh;
+  sh.view = sys->view;
+  sh.seg = sys->plan.seg;
+  sh.G = sys->plan.G;
+  sh.cpl = sys->plan.cpl;
+  sh.lds = sys->plan.lds;
+  sh.lds1 = sys->plan.lds1;
+  return sh;
 }
 
 hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                          hipStream_t st) {
-  const int L = sys->level, seg = sys->plan.seg, G = sys->plan.G;
-#define PE_X(L_, S_, G_) \
-  if (L == L_ && seg == S_ && G == G_) return dispatch_rows_lsg<L_, S_, G_>(sys, P, x, O, mode, st);
-  PE_SHAPES(PE_X)
-#undef PE_X
+  const EvalShape sh = eval_shape(sys);
+  switch (sys->level) {
+    case 1: return launch_rows<1>(sh, P, x, O, mode, st);
+    case 2: return launch_rows<2>(sh, P, x, O, mode, st);
+    case 4: return launch_rows<4>(sh, P, x, O, mode, st);
+  }
   return hipErrorInvalidValue;
 }
 
 hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
-  const int L = sys->level, seg = sys->plan.seg;
-  const int G = sys->plan.G == 2 ? 2 : 1;
-#define PE_X(L_, S_, G_) \
-  if (G_ <= 2 && L == L_ && seg == S_ && G == G_) return dispatch_adj_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(sys, P, x, v, NG, gsize, part, g, st);
-  PE_SHAPES(PE_X)
-#undef PE_X
+  const EvalShape sh = eval_shape(sys);
+  switch (sys->level) {
+    case 1: return launch_adjoint<1>(sh, P, x, v, NG, gsize, part, g, st);
+    case 2: return launch_adjoint<2>(sh, P, x, v, NG, gsize, part, g, st);
+    case 4: return launch_adjoint<4>(sh, P, x, v, NG, gsize, part, g, st);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -664,19 +576,16 @@ NewtonLayout newton_layout(int L, int N, int n, int P) {
   return lo;
 }
 
-template <int L>
-hipError_t launch_mgs(int P, int N, int n, double* W, const NewtonLayout& lo, char* base, double* x,
-                      double* resid, hipStream_t st) {
-  auto kern = mgs_solve_kernel<L, kMgsThreads>;
-  const size_t lds = mgs_lds_bytes<L>(N);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
+hipError_t dispatch_mgs(int L, int P, int N, int n, double* W, const NewtonLayout& lo, char* base, double* x,
+                        double* resid, hipStream_t st) {
+  double* R = reinterpret_cast<double*>(base + lo.r_off);
+  double* Y = reinterpret_cast<double*>(base + lo.y_off);
+  switch (L) {
+    case 1: return launch_mgs<1>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
+    case 2: return launch_mgs<2>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
+    case 4: return launch_mgs<4>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
   }
-  hipLaunchKernelGGL(kern, dim3(unsigned(P)), dim3(kMgsThreads), lds, st, N, n, W, lo.w_pt,
-                     reinterpret_cast<double*>(base + lo.r_off), lo.r_pt, reinterpret_cast<double*>(base + lo.y_off),
-                     lo.y_pt, x, int64_t(2) * L * n, resid);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 pe_status newton_check(const pe_system* sys, int P) {
@@ -724,9 +633,7 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
   O.f_sign = -1.0;
   hipError_t e = dispatch_rows(sys, P, x_inout, O, MODE_EVAL, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton eval launch: ") + hipGetErrorString(e));
-  if (L == 1) e = launch_mgs<1>(P, N, n, W, lo, base, x_inout, resid_out, hs);
-  if (L == 2) e = launch_mgs<2>(P, N, n, W, lo, base, x_inout, resid_out, hs);
-  if (L == 4) e = launch_mgs<4>(P, N, n, W, lo, base, x_inout, resid_out, hs);
+  e = dispatch_mgs(L, P, N, n, W, lo, base, x_inout, resid_out, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton solve launch: ") + hipGetErrorString(e));
   return PE_OK;
 }
@@ -770,53 +677,28 @@ struct pe_batch {
 
 namespace {
 
-template <int L, int SEG, int CPL, int G, int MODE>
-hipError_t launch_batch_t(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, hipStream_t st) {
-  const BatchClass& K = b->cls[c];
-  auto kern = batch_rows_kernel<L, SEG, CPL, G, MODE>;
-  if (K.lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(K.lds));
-    if (e != hipSuccess) return e;
-  }
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, K.lds);
-  if (e != hipSuccess) return e;
-  int dev = 0, cus = 0;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, K.nitems));
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), K.lds, st, (const SysView*)b->d_views,
-                     (const uint64_t*)K.d_items, K.nitems, b->d_counter + c, P, x, (const int64_t*)b->d_offs, out);
-  return hipGetLastError();
-}
-
-template <int L, int SEG, int G>
-hipError_t dispatch_batch_seg(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, int mode,
-                              hipStream_t st) {
-  switch (b->cls[c].cpl * 4 + mode) {
-#define PE_CASE(CPL, MODE) \
-  case CPL * 4 + MODE:     \
-    return launch_batch_t<L, SEG, CPL, G, MODE>(b, c, P, x, out, st);
-    PE_CASE(1, MODE_EVAL)
-    PE_CASE(1, MODE_FONLY)
-    PE_CASE(2, MODE_EVAL)
-    PE_CASE(2, MODE_FONLY)
-    PE_CASE(4, MODE_EVAL)
-    PE_CASE(4, MODE_FONLY)
-    PE_CASE(8, MODE_EVAL)
-    PE_CASE(8, MODE_FONLY)
-#undef PE_CASE
-  }
-  return hipErrorInvalidValue;
+__global__ void reset_counter_kernel(int* counter, int count) {
+  if (blockIdx.x == 0 && int(threadIdx.x) < count) counter[threadIdx.x] = 0;
 }
 
 hipError_t dispatch_batch_class(const pe_batch* b, int c, int P, const double* x, const BatchOut& out, int mode,
                                 hipStream_t st) {
-  const int L = b->level, seg = b->seg, G = b->cls[c].G;
-#define PE_X(L_, S_, G_) \
-  if (G_ <= 2 && L == L_ && seg == S_ && G == G_) return dispatch_batch_seg<L_, S_, (G_ <= 2 ? G_ : 1)>(b, c, P, x, out, mode, st);
-  PE_SHAPES(PE_X)
-#undef PE_X
+  const BatchClass& C = b->cls[c];
+  BatchShape K;
+  K.seg = b->seg;
+  K.G = C.G;
+  K.cpl = C.cpl;
+  K.lds = C.lds;
+  K.nitems = C.nitems;
+  K.items = C.d_items;
+  K.views = b->d_views;
+  K.x_off = b->d_offs;
+  K.counter = b->d_counter + c;
+  switch (b->level) {
+    case 1: return launch_batch<1>(K, P, x, out, mode, st);
+    case 2: return launch_batch<2>(K, P, x, out, mode, st);
+    case 4: return launch_batch<4>(K, P, x, out, mode, st);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -1047,19 +929,12 @@ pe_status pe_batch_newton_step(const pe_batch* b, int32_t P, double* x_inout, vo
   out.newton = 1;
   hipError_t e = dispatch_batch(b, P, x_inout, out, MODE_EVAL, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("batch newton eval: ") + hipGetErrorString(e));
-  size_t lds = L == 1 ? mgs_lds_bytes<1>(b->maxN) : (L == 2 ? mgs_lds_bytes<2>(b->maxN) : mgs_lds_bytes<4>(b->maxN));
-  auto go = [&](auto kern) -> hipError_t {
-    if (lds > 65536) {
-      hipError_t e2 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      if (e2 != hipSuccess) return e2;
-    }
-    hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(b->S) * P)), dim3(kMgsThreads), lds, hs,
-                       (const BatchNewtonDesc*)b->d_ndesc, (const int*)b->d_order, P, W, Rw, Yw, x_inout, resid_out);
-    return hipGetLastError();
-  };
-  if (L == 1) e = go(mgs_solve_batch_kernel<1, kMgsThreads>);
-  if (L == 2) e = go(mgs_solve_batch_kernel<2, kMgsThreads>);
-  if (L == 4) e = go(mgs_solve_batch_kernel<4, kMgsThreads>);
+  const BatchNewtonDesc* nd = b->d_ndesc;
+  switch (L) {
+    case 1: e = launch_mgs_batch<1>(b->S, P, b->maxN, nd, b->d_order, W, Rw, Yw, x_inout, resid_out, hs); break;
+    case 2: e = launch_mgs_batch<2>(b->S, P, b->maxN, nd, b->d_order, W, Rw, Yw, x_inout, resid_out, hs); break;
+    case 4: e = launch_mgs_batch<4>(b->S, P, b->maxN, nd, b->d_order, W, Rw, Yw, x_inout, resid_out, hs); break;
+  }
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("batch newton solve: ") + hipGetErrorString(e));
   return PE_OK;
 }
