@@ -1,10 +1,9 @@
 """Algorithmic work of one evaluation: FP64 flops and bytes.
 
-Operation counts are those of the arithmetic in ``csrc/mdarith.hpp``,
-counted from its source: additions, subtractions and products count 1, an
-FMA counts 2, and multiplications by +-1 (sign changes) count 0.
-
-Per complex level-L operation (flops):
+Operation counts per complex level-L operation are those of the arithmetic in
+``csrc/mdarith.hpp``, counted from its source: additions, subtractions and
+products count 1, an FMA counts 2, and multiplications by +-1 (sign changes)
+count 0.
 
 =========  ======  =======  =======
 op         L = 1   L = 2    L = 4
@@ -19,21 +18,28 @@ cmul: D one FMA and one product per component; DD the fused double-word
 two-product sum per component; QD the fused order-by-order sum of partial
 products per component.  cscal: the product of a partial derivative by its
 exponent (DD unnormalised, one product and two FMAs per component).  cadd_J:
-one slot added into a Jacobian column (DD: TwoSum on the high parts plus two
-plain additions per component, the compensated sum of the owners); cadd_F:
-one monomial value added into F.
+one contribution added into a Jacobian entry (DD: TwoSum on the high parts
+plus two plain additions per component, the compensated sum of the owners);
+cadd_F: one monomial value added into F.
 
-The algorithmic work of a monomial with k variables, l of them with exponent
-d >= 2, is the work of the reverse mode over its product of variables with
-the coefficient and the common factor folded into the seed (Sec. 2.2-2.3):
-l products for the common factor, k-1 forward products, k-1 products for the
-partial derivatives and k for the backward products (the last one gives the
-monomial's value), i.e. l + 3k - 2 complex products; k scalings by the
-exponent; k additions into J and one into F.  A constant monomial (k = 0)
-costs one addition.  The table of powers costs n (emax - 2) products per point.  The
-extra products of the library's lane decomposition (the butterfly across the
-lanes of a monomial) are not algorithmic and not counted, so a roofline
-fraction from these counts is a lower bound of the FP64 utilisation.
+Two counts of complex products per monomial of k variables, l of them with
+exponent d >= 2:
+
+* the ALGORITHMIC count of the method (Sec. 2.1-2.3): the product of the k
+  variables and all its partial derivatives by the reverse mode, 3k - 5
+  products (Sec. 2.2; none for k = 1); the common factor of the l powers
+  times the coefficient, max(l - 1, 0) + [l >= 1]; the term formation, one
+  product for the value and k for the partial derivatives (Sec. 2.3); l
+  scalings by an exponent; k + 1 additions (k into J, one into F).  This is
+  the count the roofline fractions use.
+* the EXECUTED count of the library's one-lane schedule, which folds the
+  coefficient and the common factor into the seed of the reverse sweep
+  (l products into the seed, k - 2 prefix products, 2k - 1 in the sweep:
+  l + 3k - 3, at least l + 1), plus k exponent scalings.  The butterfly that
+  joins the lanes of a monomial spanning several lanes adds products that
+  neither count includes.
+
+The table of powers (a few products per variable and point) is not counted.
 
 Bytes: the packed structure that one evaluation must read (8 bytes per
 occurrence record, 16L per monomial, 2 (n + 1) per chunk), x, and the
@@ -50,25 +56,60 @@ FLOPS = {
 }
 
 
-def monomial_counts(sys_):
-    """(cmul, cscal, cadd_J, cadd_F) totals for one point."""
+def algorithmic_products(k: int, ell: int) -> int:
+    """Complex products of one monomial by the method's own count."""
+    if k <= 0:
+        return 0
+    return max(3 * k - 5, 0) + max(ell - 1, 0) + (1 if ell >= 1 else 0) + 1 + k
+
+
+def executed_products(k: int, ell: int) -> int:
+    """Complex products of the library's one-lane schedule for one monomial."""
+    if k <= 0:
+        return 0
+    return ell + max(3 * k - 3, 1)
+
+
+def _k_and_ell(sys_):
     k = np.diff(sys_.mon_ptr).astype(np.int64)
-    hi = (sys_.exps >= 2).astype(np.int64)
     owner = np.repeat(np.arange(sys_.n_monomials), k)
     ell = np.zeros(sys_.n_monomials, np.int64)
-    np.add.at(ell, owner, hi)
+    np.add.at(ell, owner, (sys_.exps >= 2).astype(np.int64))
+    return k, ell
+
+
+def algorithmic_counts(sys_):
+    """(cmul, cscal, cadd_J, cadd_F) of the method for one point."""
+    k, ell = _k_and_ell(sys_)
     pos = k > 0
-    cmul = int(np.sum(ell[pos] + 3 * k[pos] - 2))
-    emax = int(sys_.exps.max()) if sys_.nnz else 1
-    cmul += sys_.n_vars * max(0, emax - 2)
-    cscal = int(np.sum(k))
-    return cmul, cscal, int(np.sum(k)), int(sys_.n_monomials)
+    kp, lp = k[pos], ell[pos]
+    cmul = np.maximum(3 * kp - 5, 0) + np.maximum(lp - 1, 0) + (lp >= 1) + 1 + kp
+    return int(cmul.sum()), int(ell.sum()), int(k.sum()), int(sys_.n_monomials)
+
+
+def executed_counts(sys_):
+    """(cmul, cscal, cadd_J, cadd_F) of the library's schedule for one point
+    (butterfly products excluded)."""
+    k, ell = _k_and_ell(sys_)
+    pos = k > 0
+    cmul = ell[pos] + np.maximum(3 * k[pos] - 3, 1)
+    return int(cmul.sum()), int(k.sum()), int(k.sum()), int(sys_.n_monomials)
+
+
+def _flops(level, counts) -> float:
+    f = FLOPS[level]
+    cmul, cscal, cadd_j, cadd_f = counts
+    return float(cmul * f["cmul"] + cscal * f["cscal"] + cadd_j * f["cadd_J"] + cadd_f * f["cadd_F"])
 
 
 def flops_per_point(sys_) -> float:
-    f = FLOPS[sys_.level]
-    cmul, cscal, cadd_j, cadd_f = monomial_counts(sys_)
-    return float(cmul * f["cmul"] + cscal * f["cscal"] + cadd_j * f["cadd_J"] + cadd_f * f["cadd_F"])
+    """Algorithmic FP64 flops of one evaluation of F and J at one point."""
+    return _flops(sys_.level, algorithmic_counts(sys_))
+
+
+def executed_flops_per_point(sys_) -> float:
+    """FP64 flops of the library's schedule at one point."""
+    return _flops(sys_.level, executed_counts(sys_))
 
 
 def bytes_per_point(sys_, want_J: bool = True, chunks: int | None = None) -> float:

@@ -390,10 +390,111 @@ def pin_gauss_newton_quadratic() -> bool:
     return errs[-1] < 1e-58
 
 
+# ---------------------------------------------------------------- columns and normalisers
+
+def pin_columns_match_rows() -> bool:
+    """The column-wise evaluation (used for sampled columns and the adjoint)
+    equals the row-wise one, transposed, exactly: random systems with
+    exponents up to 4 at every level; and the adjoint by columns equals
+    sum_p conj(J_pj) v_p over the row-wise J."""
+    import oracle.exact as OE
+    for L, seed in ((1, 401), (2, 402), (4, 403)):
+        sys_ = synth.random_system(seed, L, n_vars=9, n_polys=6, m=5, k=4, exp_lo=1, exp_hi=4)
+        x = synth.unit_circle_points(synth.rng_for(seed + 10), 1, 9, L)[0]
+        _, J = OE.eval_rows(sys_, x, range(6))
+        cols = OE.eval_columns(sys_, x, range(9))
+        for j in range(9):
+            want = {p: J[p][j] for p in range(6) if j in J[p]}
+            if set(cols[j]) != set(want):
+                return False
+            for p, val in want.items():
+                if not OE.cdy_is_zero(OE.cdy_add(cols[j][p], OE.cdy_neg(val))):
+                    return False
+        v = synth.unit_circle_points(synth.rng_for(seed + 20), 1, 6, L)[0]
+        g = OE.adjoint_exact(J, OE.point_from_limbs(v), 9)
+        gc = OE.adjoint_columns(sys_, x, v, range(9))
+        if any(not OE.cdy_is_zero(OE.cdy_add(gc[j], OE.cdy_neg(g[j]))) for j in range(9)):
+            return False
+    return True
+
+
+def pin_abs_sums_positive() -> bool:
+    """When every coefficient and every variable is a positive real, all
+    terms of F_p and of J_pj are positive, so the sum of their absolute
+    values equals the absolute value of the exact sum: S_F(p) = |F_p| and
+    S_J(p, j) = |J_pj|, by rows and by columns (moduli 2^a, a in -2..2, and
+    small integer coefficients, so the float sums are exact)."""
+    import oracle.exact as OE
+    rng = synth.rng_for(411)
+    sys_ = synth.random_system(412, 2, n_vars=7, n_polys=5, m=6, k=3, exp_lo=1, exp_hi=4)
+    sys_.coef[:] = 0.0
+    sys_.coef[0, 0] = rng.integers(1, 6, size=sys_.n_monomials)
+    x = np.zeros((2, 2, 7))
+    x[0, 0] = np.ldexp(1.0, rng.integers(-2, 3, size=7))
+    F, J = OE.eval_rows(sys_, x, range(5))
+    SF, SJ = OE.abs_sums_rows(sys_, x, range(5))
+    Sc = OE.abs_sums_columns(sys_, x, range(7))
+    for p in range(5):
+        if SF[p] != OE.cdy_abs_float(F[p]):
+            return False
+        if set(SJ[p]) != set(J[p]):
+            return False
+        for j, val in J[p].items():
+            if SJ[p][j] != OE.cdy_abs_float(val) or Sc[j].get(p) != SJ[p][j]:
+                return False
+    return all(set(Sc[j]) == {p for p in range(5) if j in J[p]} for j in range(7))
+
+
+def pin_error_metric_rejects() -> bool:
+    """The checker itself: the exact value rounded to limbs scores at most
+    the rounding error; an entry moved by 10 tau S fails a tolerance tau and
+    one moved by tau S / 10 passes; a nonzero entry where S = 0 scores inf;
+    a wrong entry planted in a whole F/J comparison, or two columns of J
+    swapped, are found."""
+    import oracle.exact as OE
+    tau = 1e-28
+    L = 2
+    sys_ = synth.random_system(421, L, n_vars=6, n_polys=4, m=5, k=3, exp_lo=1, exp_hi=3)
+    x = synth.unit_circle_points(synth.rng_for(422), 1, 6, L)[0]
+    F, J = OE.eval_rows(sys_, x, range(4))
+    SF, SJ = OE.abs_sums_rows(sys_, x, range(4))
+    Fl = np.stack([OE.cdy_to_limbs(F[p], L) for p in range(4)], axis=-1)
+    Jl = np.zeros((2, L, 4, 6))
+    for p in range(4):
+        for j, v in J[p].items():
+            Jl[:, :, p, j] = OE.cdy_to_limbs(v, L)
+    eF, eJ = OE.max_rel_error_rows(sys_, x, Fl, Jl, range(4))
+    if not (eF <= 2.0 ** -104 and eJ <= 2.0 ** -104):
+        return False
+    p = 2
+    for scale, must_fail in ((10.0, True), (0.1, False)):
+        # move the real part by scale * tau * S_F(p), exactly (dyadic shift)
+        m, e = OE.dy_from_float(scale * tau * SF[p])
+        moved = OE.cdy_add(F[p], (m, 0, e))
+        lim = OE.cdy_to_limbs(moved, L)
+        err = OE.rel_error(lim[0], lim[1], F[p], SF[p])
+        if (err > tau) != must_fail:
+            return False
+    if OE.rel_error([1e-300, 0.0], [0.0, 0.0], OE.ZERO, 0.0) != math.inf:
+        return False
+    if OE.rel_error([0.0, 0.0], [0.0, 0.0], OE.ZERO, 0.0) != 0.0:
+        return False
+    bad = Jl.copy()
+    j = next(iter(J[1]))
+    bad[0, 1, 1, j] += 1e-20 * SJ[1][j]
+    if OE.max_rel_error_rows(sys_, x, Fl, bad, range(4))[1] <= tau:
+        return False
+    cols = sorted(J[3])
+    swapped = Jl.copy()
+    swapped[:, :, 3, [cols[0], cols[1]]] = Jl[:, :, 3, [cols[1], cols[0]]]
+    return OE.max_rel_error_rows(sys_, x, Fl, swapped, range(4))[1] > tau
+
+
 ALL_PINS = [
     pin_speelpenning_closed_form, pin_speelpenning_figures, pin_speelpenning_euler,
     pin_linear_system, pin_linear_adjoint, pin_univariate, pin_univariate_mpmath,
     pin_quadratic_form, pin_finite_differences, pin_euler_homogeneity,
     pin_cyclic_at_one, pin_cyclic_at_roots_of_unity, pin_limb_rounding, pin_abs_sums,
-    pin_gauss_newton_linear, pin_gauss_newton_quadratic,
+    pin_gauss_newton_linear, pin_gauss_newton_quadratic, pin_columns_match_rows,
+    pin_abs_sums_positive, pin_error_metric_rejects,
 ]

@@ -154,6 +154,105 @@ def _make_eval_rows_transposed():
     return eval_rows
 
 
+def _make_eval_columns(exp_factor_shift=0, drop_common=False):
+    def eval_columns(sys_, x, cols):
+        X = E.point_from_limbs(x)
+        cols = [int(c) for c in cols]
+        out = {j: {} for j in cols}
+        want = set(cols)
+        for p in range(sys_.n_polys):
+            for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+                vs, ds = sys_.monomial(t)
+                hit = [r for r, v in enumerate(vs) if int(v) in want]
+                if not hit:
+                    continue
+                c = E._coef(sys_, t)
+                xs = [X[v] for v in vs]
+                pw = [E._power(xs[s], ds[s]) for s in range(len(vs))]
+                for r in hit:
+                    g = E.cdy_scale(c, int(ds[r]) - exp_factor_shift)
+                    if not drop_common:
+                        g = E.cdy_mul(g, E._power(xs[r], ds[r] - 1))
+                    for s in range(len(vs)):
+                        if s != r:
+                            g = E.cdy_mul(g, pw[s])
+                    j = int(vs[r])
+                    out[j][p] = E.cdy_add(out[j][p], g) if p in out[j] else g
+        return out
+    return eval_columns
+
+
+def _make_abs_sums_columns_no_exponent():
+    import math as _m
+    import numpy as _np
+
+    def abs_sums_columns(sys_, x, cols):
+        ax = _np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+        ac = _np.hypot(sys_.coef[0].sum(axis=0), sys_.coef[1].sum(axis=0))
+        cols = [int(c) for c in cols]
+        want = set(cols)
+        out = {j: {} for j in cols}
+        for p in range(sys_.n_polys):
+            for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+                vs, ds = sys_.monomial(t)
+                pw = [float(ax[v]) ** int(d) for v, d in zip(vs, ds)]
+                for r, v in enumerate(vs):
+                    if int(v) not in want:
+                        continue
+                    g = float(ac[t]) * float(ax[v]) ** (int(ds[r]) - 1)  # exponent factor dropped
+                    g *= _m.prod(pw[s] for s in range(len(vs)) if s != r)
+                    out[int(v)][p] = out[int(v)].get(p, 0.0) + g
+        return out
+    return abs_sums_columns
+
+
+def _make_abs_sums_rows_no_power():
+    orig = E.abs_sums_rows
+
+    def abs_sums_rows(sys_, x, rows):
+        import numpy as _np
+        ax = _np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+        ac = _np.hypot(sys_.coef[0].sum(axis=0), sys_.coef[1].sum(axis=0))
+        SF, SJ = {}, {}
+        for p in rows:
+            sf, sj = 0.0, {}
+            for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+                vs, ds = sys_.monomial(t)
+                pw = [float(ax[v]) ** int(d) for v, d in zip(vs, ds)]
+                m = float(ac[t])
+                for w in pw:
+                    m *= w
+                sf += m
+                for r, v in enumerate(vs):
+                    g = float(ac[t]) * int(ds[r])  # |x_j|^(d-1) dropped
+                    for s in range(len(vs)):
+                        if s != r:
+                            g *= pw[s]
+                    sj[int(v)] = sj.get(int(v), 0.0) + g
+            SF[p], SJ[p] = sf, sj
+        return SF, SJ
+    del orig
+    return abs_sums_rows
+
+
+def _mut_rel_error_zero_scale_ok(got_re, got_im, exact, S):
+    g = E.cdy_from_limbs(got_re, got_im)
+    d = E.cdy_add(g, E.cdy_neg(exact))
+    if E.cdy_is_zero(d) or S == 0.0:
+        return 0.0
+    return E.cdy_abs_float(d) / S
+
+
+def _mut_rel_error_lenient(got_re, got_im, exact, S):
+    g = E.cdy_from_limbs(got_re, got_im)
+    d = E.cdy_add(g, E.cdy_neg(exact))
+    if E.cdy_is_zero(d):
+        return 0.0
+    if S == 0.0:
+        return float("inf")
+    return E.cdy_abs_float(d) / (1e6 * S)
+
+
 MUTANTS = {
     "power_off_by_one": ("_power", _mut_power_off_by_one),
     "mul_sign": ("cdy_mul", _mut_mul_sign),
@@ -167,6 +266,12 @@ MUTANTS = {
     "limbs_drop_last": ("cdy_from_limbs", _mut_from_limbs_drop_last),
     "sum_drops_last_monomial": ("eval_rows", _make_eval_rows_drop_last_monomial()),
     "J_transposed": ("eval_rows", _make_eval_rows_transposed()),
+    "columns_exponent_factor_e": ("eval_columns", _make_eval_columns(exp_factor_shift=1)),
+    "columns_drop_common_factor": ("eval_columns", _make_eval_columns(drop_common=True)),
+    "abs_columns_no_exponent": ("abs_sums_columns", _make_abs_sums_columns_no_exponent()),
+    "abs_rows_no_power": ("abs_sums_rows", _make_abs_sums_rows_no_power()),
+    "metric_zero_scale_accepts": ("rel_error", _mut_rel_error_zero_scale_ok),
+    "metric_lenient": ("rel_error", _mut_rel_error_lenient),
 }
 
 

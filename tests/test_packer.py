@@ -135,3 +135,18 @@ def test_chunk_budget(lib):
     assert np.all(P["chunks"][:, 5] + 1 <= 1100)
     assert np.all(P["chunks"][:, 6] <= 256)
     check_rowdesc(P, s.n_polys)
+
+
+def test_packer_under_sanitizers(tmp_path):
+    """The validator and packer, built with g++ and the address and
+    undefined-behaviour sanitizers, over random and malformed systems."""
+    exe = tmp_path / "pack_fuzz"
+    build = subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                            "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                            os.path.join(HERE, "pack_fuzz.cpp"), os.path.join(SRC, "packer.cpp"), "-o", str(exe)],
+                           capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    run = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=600)
+    assert run.returncode == 0 and run.stdout.strip().endswith("OK"), run.stdout[-2000:] + run.stderr[-4000:]
