@@ -1,55 +1,57 @@
-"""Benchmark: evaluation of F and the full Jacobian of a sparse polynomial
-system at a complex point, in complex double double.
+"""Benchmark: evaluation of F and the full Jacobian of sparse polynomial
+systems at complex points, by the reverse mode on each monomial.
 
-Workload: n = 256 variables, N = 256 polynomials of 256 monomials each, every
-monomial the product of k = 16 distinct variables (uniform without
-replacement) with exponents uniform in {1..4}, unit-circle coefficients and
-point (seeded, synthetic).  One step is one pe_eval call computing F and the
-256 x 256 J at one point; inputs are resident in HBM.
+Default workload (the largest single-GPU one): 4096 uneven complex
+double-double systems, n = N = m drawn uniformly from {32, 64, 128, 256}, every
+monomial the product of k = min(16, n/4) distinct variables (uniform without
+replacement) with exponents uniform in {1, 2, 3}, unit-circle coefficients and
+points (seeded, synthetic), each system evaluated at 8 points.  One step is
+one pe_batch_eval call (the persistent launches over every system-point);
+inputs are resident in HBM.  Beside it the plain path, one pe_eval launch per
+system-point, is timed on the same GPU.
 
 Prints one JSON line: monomial evaluations (value and all partials, summed
-into F and J) per second, the roofline of the evaluation kernel, and the CPU
-oracle timed on a bounded sample.
+into F and J) per second, the roofline of the evaluation kernels by the
+method's operation count, and the CPU oracle timed on a bounded sample.
+Other workloads (--workload) print the same kind of line for context.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "dd_n256"
+WORKLOAD = "dd_batch4096"
+METRIC = "monomial eval+grad/s and F+J per s (complex D/DD/QD); % of FP64 or HBM roofline"
 LEVEL_NAME = {1: "double", 2: "double-double", 4: "quad-double"}
-
-
-def describe(name):
-    from paper_1402_2626_amd import synth
-    if name == "dd_batch4096":
-        return ("dd_batch4096: 4096 systems, n = N = m uniform in {32,64,128,256}, k = min(16, n/4), "
-                "exps {1..3}, 8 points each, one persistent launch")
-    w = synth.WORKLOADS[name]
-    return (f"{name}: n={w['n']}, N={w['N']}, {w['m']} monomials/poly, k={w['k']}, "
-            f"exps {{1..{w['exp_hi']}}}, {w['P']} point(s)")
 PEAK_FP64_TFLOPS = 78.6  # 256 CUs x 64 FP64 FMA lanes/clk x 2 flops x 2.4 GHz
 PEAK_HBM_GBS = 8000.0    # HBM3E
+# the machine's CPU share for one GPU: worker pools never exceed it, whatever the
+# host's core count
+CPU_SHARE = 16
 
-# HBM bytes of the evaluation kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# passes (KiB per dispatch) scaled by what the same counters read for a plain
-# device copy of known size.  The figures hold for the kernel sources they
-# were taken with: `traffic` is null when the sources have changed since.
-COUNTERS = {"dd_n256": os.path.join(ROOT, "profiles", "eval_rows_dd_n256_counters.json"),
-            "d_product_65024x1024": os.path.join(ROOT, "profiles", "eval_rows_d_product_counters.json")}
-KERNEL_SOURCES = ["eval_kernels.hpp", "mdarith.hpp", "layout.hpp", "polyeval.hip", "packer.cpp", "packer.hpp"]
+BATCH_COUNT, BATCH_POINTS = 4096, 8
+
+# rocprofv3 counter summaries per workload: HBM bytes (FETCH_SIZE, WRITE_SIZE
+# per dispatch, scaled by what the same counters read for a plain device copy
+# of known size) and FP64 instruction counts.  They hold for the kernel
+# sources they were taken with: the bench reports them only while the
+# sources match.
+COUNTERS_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["eval_kernels.hpp", "mdarith.hpp", "layout.hpp", "polyeval.hip", "packer.cpp", "packer.hpp",
+                  "launch.hpp", "instances.hip", "newton_kernels.hpp"]
 
 
 def kernel_source_digest() -> str:
-    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1402_2626_amd", "csrc", f), "rb") as fh:
@@ -57,155 +59,77 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(workload: str):
-    """HBM bytes per launch of the evaluation kernel, or None."""
+def load_counters(workload: str):
+    """The counter summary of a workload if it matches the current sources."""
     try:
-        with open(COUNTERS[workload]) as fh:
+        with open(os.path.join(COUNTERS_DIR, f"counters_{workload}.json")) as fh:
             c = json.load(fh)
-    except (KeyError, OSError, ValueError):
+    except (OSError, ValueError):
         return None
     if c.get("workload") != workload or c.get("source_sha256") != kernel_source_digest():
         return None
-    return (c["fetch_kib_per_dispatch"] * c["fetch_scale"] + c["write_kib_per_dispatch"] * c["write_scale"]) * 1024.0
+    return c
 
 
-def cpu_baseline(sys_, x, rows: int):
-    """The exact oracle on the first `rows` polynomials (F and full rows of
-    J) at the same point, spread over the host cores; returns monomials/s,
-    the cores used and the wall time."""
+def counter_traffic(c):
+    """HBM bytes per step: FETCH and WRITE of the step's kernels, scaled."""
+    if not c:
+        return None
+    return sum((k["fetch_kib_per_dispatch"] * c["fetch_scale"] + k["write_kib_per_dispatch"] * c["write_scale"])
+               * 1024.0 * k.get("dispatches_per_step", 1) for k in c["kernels"])
+
+
+def fp64_issue_fraction(c, step_ms):
+    """FP64 VALU instructions per step over what the SIMDs can issue in the
+    step's time: a wave64 FP64 instruction occupies a SIMD for 4 cycles, 4
+    SIMDs per CU, 256 CUs, 2.4 GHz.  None without counters."""
+    if not c or "fp64_wave_insts_per_step" not in c:
+        return None
+    slots = step_ms * 1e-3 * 2.4e9 * 256 * 4 / 4.0
+    return c["fp64_wave_insts_per_step"] / slots
+
+
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def run_oracle_jobs(fn, jobs):
+    """Run oracle jobs on min(CPU share, cores) spawned workers; returns
+    (results, wall seconds, workers)."""
     import multiprocessing as mp
-
-    cores = max(1, min(16, os.cpu_count() or 1))
-    rr = list(range(rows))
-    per = max(1, (rows + cores - 1) // cores)
-    jobs = [(sys_, x[0], rr[a:a + per]) for a in range(0, rows, per)]
+    workers = max(1, min(CPU_SHARE, os.cpu_count() or 1, len(jobs)))
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(min(cores, len(jobs))) as pool:
-        pool.map(_oracle_rows, jobs)
-    dt = time.perf_counter() - t0
-    m = int(sys_.poly_ptr[rows] - sys_.poly_ptr[0])
-    return m / dt, min(cores, len(jobs)), dt
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(fn, jobs)
+    return res, time.perf_counter() - t0, workers
 
 
 def _oracle_rows(args):
     import oracle as O
     sys_, x, rows = args
     O.eval_rows(sys_, x, rows, want_J=True)
-    return len(rows)
+    return int(sum(int(sys_.poly_ptr[p + 1] - sys_.poly_ptr[p]) for p in rows))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-rows", type=int, default=96)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
-                    help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
-    ap.add_argument("--shapes", action="store_true",
-                    help="time every compiled launch shape of the workload (one line each) and exit")
-    ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing")
-    ap.add_argument("--workload", default=WORKLOAD,
-                    help="dd_n256 (default, the reported line); d_n32, qd_n1024, dd_adjoint_1024x512, "
-                         "dd_batch4096, d_product_65024x1024, cyclic_d_n512 and cyclic_dd_n512 print the "
-                         "same kind of line for context")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(rows of F and J would shard across GPUs with no exchange)", file=sys.stderr)
-        sys.exit(2)
-
-    from paper_1402_2626_amd import synth
-    from paper_1402_2626_amd import workmodel as W
-
-    if args.copy_reference:
-        import torch
-        a = torch.ones(args.copy_reference << 17, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_reference_bytes": a.numel() * 8, "launches": 3}), flush=True)
-        return
-    if args.workload == "dd_batch4096":
-        return bench_batch(args)
-    if args.workload == "dd_adjoint_1024x512":
-        return bench_adjoint(args)
-    if args.workload == "d_product_65024x1024":
-        return bench_product(args)
-    if args.workload in CYCLIC:
-        return bench_cyclic(args)
-    sys_, x = synth.workload(args.workload)
-    P = x.shape[0]
-
-    cpu = None
-    if not args.no_cpu:
-        v, cores, dt = cpu_baseline(sys_, x, args.cpu_rows)
-        cpu = {"value": v, "unit": "monomials/s", "cores": cores, "kind": "oracle",
-               "sample": f"{args.cpu_rows} of {sys_.n_polys} polynomials (F and full J rows, "
-                         f"exact arithmetic) at the same point, {dt:.1f} s wall"}
-
-    import torch
-    from paper_1402_2626_amd import polyeval as pe
-
-    dev = torch.device("cuda:0")
-    S = pe.System.from_sparse(sys_)
-    if args.shapes:
-        xd = torch.from_numpy(x).to(dev)
-        st = torch.cuda.current_stream()
-        for seg in (2, 4, 8, 16):
-            for G in (1, 2, 4):
-                try:
-                    S.set_shape(G, segment=seg)
-                except pe.PolyevalError:
-                    continue
-                dt, ms = _time_steps(lambda: S.eval(xd, stream=st), args.steps, args.warmup, st)
-                print(json.dumps({"workload": args.workload, "segment": seg, "chunks_per_workgroup": G,
-                                  "kernel_ms": ms, "step_ms": dt / args.steps * 1e3,
-                                  "lds_bytes": S.info()["lds_bytes"]}), flush=True)
-        return
-    if args.autotune:
-        S.autotune(P)
-    xd = torch.from_numpy(x).to(dev)
-    F = torch.empty((P, 2, sys_.level, sys_.n_polys), dtype=torch.float64, device=dev)
-    J = torch.empty((P, 2, sys_.level, sys_.n_polys, sys_.n_vars), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        S.eval(xd, out=(F, J), stream=stream)
-    torch.cuda.synchronize()
-
-    # timed region: K steps, each one pe_eval (one kernel launch), enqueued
-    # back to back; HIP events on the launch stream bracket the region, so
-    # their interval / K is the average launch duration
-    K = args.steps
-    dt, kern_ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=stream), K, 0, stream)
-
-    M = sys_.n_monomials
-    flops = W.flops_per_point(sys_) * P
-    achieved = flops / (kern_ms * 1e-3) / 1e12
-    out = {
-        "metric": "monomial eval+grad/s (complex %s, F + full J)" % LEVEL_NAME[sys_.level],
-        "value": M * P * K / dt,
-        "unit": "monomials/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": dt / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 (%s complex)" % LEVEL_NAME[sys_.level],
-        "data": "synthetic",
-        "config": {"workload": describe(args.workload),
-                   "points": P, "monomials": M, "occurrences": sys_.nnz,
-                   "F_plus_J_per_s": P * K / dt, "kernel_ms": kern_ms},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": counter_traffic(args.workload)},
-        "cpu_baseline": cpu,
-    }
-    S.close()
-    print(json.dumps(out), flush=True)
+def cpu_baseline_rows(sys_, x, rows):
+    """The exact oracle on the given rows (F and full rows of J) at point x."""
+    model, ncpu = host_cpu()
+    rows = list(rows)
+    per = max(1, (len(rows) + CPU_SHARE - 1) // CPU_SHARE)
+    jobs = [(sys_, x, rows[a:a + per]) for a in range(0, len(rows), per)]
+    res, dt, workers = run_oracle_jobs(_oracle_rows, jobs)
+    return {"value": sum(res) / dt, "unit": "monomials/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(rows)} of {sys_.n_polys} polynomials (F and full J rows, exact arithmetic) at one "
+                      f"point, {dt:.1f} s wall", "cpu_model": model, "host_cpus": ncpu}
 
 
 def _time_steps(fn, K, W, stream):
@@ -227,6 +151,175 @@ def _time_steps(fn, K, W, stream):
     return dt, e0.elapsed_time(e1) / K
 
 
+def line(workload_desc, level, value, K, W, dt, extra_config, roofline, cpu):
+    return {"metric": METRIC, "value": value, "unit": "monomials/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64 (%s complex)" % LEVEL_NAME[level], "data": "synthetic",
+            "config": dict({"workload": workload_desc}, **extra_config), "roofline": roofline, "cpu_baseline": cpu}
+
+
+def alu_roofline(flops, ms, counters=None):
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": counter_traffic(counters)}
+
+
+# ------------------------------------------------------------------ the batch
+
+def _oracle_batch(args):
+    import oracle as O
+    from paper_1402_2626_amd import synth
+    i, n, rows = args
+    sys_ = synth.batch_system(0, i, n)
+    x = synth.unit_circle_points(synth.rng_for((0, 9, i)), 1, n, 2)[0]
+    O.eval_rows(sys_, x, rows, want_J=True)
+    return int(sum(int(sys_.poly_ptr[p + 1] - sys_.poly_ptr[p]) for p in rows))
+
+
+def batch_cpu_baseline(ns):
+    """The oracle on 64 systems of the batch, 16 of each size, three rows
+    each (first, middle, last) at one point."""
+    model, ncpu = host_cpu()
+    jobs = []
+    for n in (32, 64, 128, 256):
+        idx = [i for i in range(len(ns)) if int(ns[i]) == n][:16]
+        jobs += [(i, n, [0, n // 2, n - 1]) for i in idx]
+    res, dt, workers = run_oracle_jobs(_oracle_batch, jobs)
+    return {"value": sum(res) / dt, "unit": "monomials/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(jobs)} systems of the batch (16 per size n), rows 0, n/2 and n-1 of each (F and full "
+                      f"J rows, exact arithmetic) at one point, {dt:.1f} s wall", "cpu_model": model,
+            "host_cpus": ncpu}
+
+
+def bench_batch(args):
+    """4096 uneven DD systems at 8 points each in persistent launches, beside
+    the plain path (one pe_eval launch per system-point)."""
+    import numpy as np
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    S_count, P = BATCH_COUNT, BATCH_POINTS
+    ns = synth.batch_sizes(0, S_count)
+    cpu = None if args.no_cpu else batch_cpu_baseline(ns)
+    t0 = time.perf_counter()
+    dev, flops, flops_exec, mons, occ = [], 0.0, 0.0, 0, 0
+    for i in range(S_count):
+        sy = synth.batch_system(0, i, int(ns[i]))
+        dev.append(pe.System.from_sparse(sy))
+        flops += W.flops_per_point(sy) * P
+        flops_exec += W.executed_flops_per_point(sy) * P
+        mons += sy.n_monomials * P
+        occ += sy.nnz * P
+        del sy
+        if i % 512 == 511:
+            print(f"# loaded {i + 1} systems, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    B = pe.Batch(dev)
+    rng = synth.rng_for((0, 9))
+    x = torch.from_numpy(np.concatenate([synth.unit_circle_points(rng, P, int(n), 2).reshape(-1)
+                                         for n in ns])).cuda()
+    F = torch.empty(int(B.F_off[-1]) * P, dtype=torch.float64, device="cuda")
+    J = torch.empty(int(B.J_off[-1]) * P, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K = max(1, args.steps)
+    Wm = max(1, args.warmup)
+    print("# timing the batch", file=sys.stderr, flush=True)
+    dt, ms = _time_steps(lambda: B.eval(x, P, out=(F, J), stream=st), K, Wm, st)
+
+    # plain path: one pe_eval launch per system-point (and, for context, one
+    # per system at its 8 points), into the same outputs; the launch
+    # arguments are computed beforehand so the loop is the C calls only
+    import ctypes
+    lib, sp = pe._lib, ctypes.c_void_p(st.cuda_stream)
+    xb, fb, jb = x.data_ptr(), F.data_ptr(), J.data_ptr()
+    per_point, per_system = [], []
+    for i in range(S_count):
+        n = int(ns[i])
+        xo, fo, jo = int(B.x_off[i]) * P, int(B.F_off[i]) * P, int(B.J_off[i]) * P
+        h = dev[i].handle
+        per_system.append((h, P, xb + 8 * xo, fb + 8 * fo, jb + 8 * jo))
+        for p in range(P):
+            per_point.append((h, 1, xb + 8 * (xo + p * 4 * n), fb + 8 * (fo + p * 4 * n),
+                              jb + 8 * (jo + p * 4 * n * n)))
+
+    def plain_points():
+        for h, npts, xp, fp, jp in per_point:
+            lib.pe_eval(h, npts, xp, fp, jp, sp)
+
+    def plain_systems():
+        for h, npts, xp, fp, jp in per_system:
+            lib.pe_eval(h, npts, xp, fp, jp, sp)
+    print("# timing the plain path", file=sys.stderr, flush=True)
+    dt_pts, ms_pts = _time_steps(plain_points, 1, 1, st)
+    dt_sys, ms_sys = _time_steps(plain_systems, 1, 1, st)
+    info = B.info()
+    counters = load_counters("dd_batch4096")
+    out = line("batched complex double-double: 4096 systems, n = N = m uniform in {32, 64, 128, 256}, "
+               "k = min(16, n/4), exponents {1, 2, 3}, 8 points each", 2, mons * K / dt, K, Wm, dt,
+               {"system_points_per_s": S_count * P * K / dt, "F_plus_J_per_s": S_count * P * K / dt,
+                "monomials": mons, "occurrences": occ, "kernel_ms": ms,
+                "plain_per_system_point_ms": ms_pts, "plain_per_system_point_launches": S_count * P,
+                "speedup_vs_plain_per_system_point": ms_pts / ms,
+                "plain_per_system_ms": ms_sys, "speedup_vs_plain_per_system": ms_sys / ms,
+                "segment": info["segment"], "chunks_per_workgroup": info["chunks_per_workgroup"],
+                "flops_method_count": flops, "frac_executed_count": flops_exec / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                "fp64_issue_frac": fp64_issue_fraction(counters, ms)},
+               alu_roofline(flops, ms, counters), cpu)
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ single systems
+
+def bench_single(args):
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    sys_, x = synth.workload(args.workload)
+    P = x.shape[0]
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_rows(sys_, x[0], range(min(args.cpu_rows, sys_.n_polys)))
+    S = pe.System.from_sparse(sys_)
+    xd = torch.from_numpy(x).cuda()
+    st = torch.cuda.current_stream()
+    if args.shapes:
+        for seg in (2, 4, 6, 8, 16):
+            for G in (1, 2, 4):
+                try:
+                    S.set_shape(G, segment=seg)
+                except pe.PolyevalError:
+                    continue
+                dt, ms = _time_steps(lambda: S.eval(xd, stream=st), args.steps, args.warmup, st)
+                print(json.dumps({"workload": args.workload, "segment": seg, "chunks_per_workgroup": G,
+                                  "kernel_ms": ms, "step_ms": dt / args.steps * 1e3,
+                                  "lds_bytes": S.info()["lds_bytes"]}), flush=True)
+        return
+    if args.autotune:
+        S.autotune(P)
+    F = torch.empty((P, 2, sys_.level, sys_.n_polys), dtype=torch.float64, device="cuda")
+    J = torch.empty((P, 2, sys_.level, sys_.n_polys, sys_.n_vars), dtype=torch.float64, device="cuda")
+    K = args.steps
+    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, args.warmup, st)
+    counters = load_counters(args.workload)
+    flops = W.flops_per_point(sys_) * P
+    w = synth.WORKLOADS[args.workload]
+    desc = (f"complex {LEVEL_NAME[sys_.level]}: n = {w['n']}, N = {w['N']}, {w['m']} monomials per polynomial, "
+            f"k = {w['k']}, exponents 1..{w['exp_hi']}, {P} point(s)")
+    info = S.info()
+    out = line(desc, sys_.level, sys_.n_monomials * P * K / dt, K, args.warmup, dt,
+               {"name": args.workload, "points": P, "monomials": sys_.n_monomials, "occurrences": sys_.nnz,
+                "F_plus_J_per_s": P * K / dt, "kernel_ms": ms, "segment": info["segment"],
+                "chunks_per_workgroup": info["chunks_per_workgroup"],
+                "frac_executed_count": W.executed_flops_per_point(sys_) * P / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                "fp64_issue_frac": fp64_issue_fraction(counters, ms)},
+               alu_roofline(flops, ms, counters), cpu)
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args):
     """g = J^H v for the overdetermined DD system (N = 1024, n = 512, k = 24)
     at 64 points; J is never formed."""
@@ -244,15 +337,12 @@ def bench_adjoint(args):
     st = torch.cuda.current_stream()
     dt, ms = _time_steps(lambda: S.adjoint(xd, vd, out=g, stream=st), args.steps, args.warmup, st)
     flops = W.flops_per_point(sys_) * P
-    out = {"metric": "monomial adjoint (J^H v) evals/s (complex double-double)",
-           "value": sys_.n_monomials * P * args.steps / dt, "unit": "monomials/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 (double-double complex)",
-           "data": "synthetic", "config": {"workload": describe("dd_adjoint_1024x512"), "points": P,
-                                           "step_ms_events": ms},
-           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
-           "cpu_baseline": None}
+    counters = load_counters("dd_adjoint_1024x512")
+    out = line("adjoint J^H v, complex double-double: N = 1024 polynomials in n = 512 variables, 512 monomials "
+               "each, k = 24, exponents 1..3, 64 points", 2, sys_.n_monomials * P * args.steps / dt, args.steps,
+               args.warmup, dt, {"points": P, "kernel_ms": ms, "fp64_issue_frac": fp64_issue_fraction(counters, ms)},
+               alu_roofline(flops, ms, counters), None)
+    S.close()
     print(json.dumps(out), flush=True)
 
 
@@ -276,18 +366,16 @@ def bench_cyclic(args):
     J = torch.empty((1, 2, L, n, n), dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
     K = min(args.steps, 50)
-    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, min(args.warmup, 5), st)
+    Wm = min(args.warmup, 5)
+    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, Wm, st)
     flops = W.flops_per_point(sys_)
-    out = {"metric": "monomial eval+grad/s (complex %s, F + full J)" % LEVEL_NAME[L],
-           "value": sys_.n_monomials * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K,
-           "warmup": min(args.warmup, 5), "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64 (%s complex)" % LEVEL_NAME[L], "data": "synthetic",
-           "config": {"workload": "%s: cyclic n-roots, n=%d, %d monomials, 1 point" % (args.workload, n, sys_.n_monomials),
-                      "kernel_ms": ms, "segment": S.info()["segment"],
-                      "paper_table5_ms_context": paper_ms},
-           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
-           "cpu_baseline": None}
+    nbytes = W.bytes_per_point(sys_, want_J=True)
+    counters = load_counters(args.workload)
+    cfg = {"name": args.workload, "kernel_ms": ms, "segment": S.info()["segment"], "monomials": sys_.n_monomials,
+           "paper_table5_ms_context": paper_ms, "hbm_frac_algorithmic_bytes": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "fp64_issue_frac": fp64_issue_fraction(counters, ms)}
+    out = line(f"cyclic {n}-roots (eq. (5)), complex {LEVEL_NAME[L]}, F and J at one unit-circle point", L,
+               sys_.n_monomials * K / dt, K, Wm, dt, cfg, alu_roofline(flops, ms, counters), None)
     S.close()
     print(json.dumps(out), flush=True)
 
@@ -308,80 +396,61 @@ def bench_product(args):
     J = torch.empty((1, 2, 1, sys_.n_polys, sys_.n_vars), dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
     K = min(args.steps, 50)
-    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, min(args.warmup, 5), st)
-    chunks = sys_.n_polys  # one chunk per polynomial
-    nbytes = W.bytes_per_point(sys_, want_J=True, chunks=chunks)
+    Wm = min(args.warmup, 5)
+    dt, ms = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, Wm, st)
+    nbytes = W.bytes_per_point(sys_, want_J=True, chunks=sys_.n_polys)
     gbs = nbytes / (ms * 1e-3) / 1e9
-    out = {"metric": "monomial eval+grad/s (complex double, F + full J)",
-           "value": sys_.n_monomials * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K,
-           "warmup": min(args.warmup, 5), "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64 (double complex)", "data": "synthetic",
-           "config": {"workload": "d_product_65024x1024: 65,024 polynomials, each one monomial of all "
-                                  "n=1,024 variables (exponent 1), 1 point; dense J of 1.07 GB",
-                      "kernel_ms": ms, "algorithmic_bytes": nbytes,
-                      "flops": W.flops_per_point(sys_)},
-           "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": gbs / PEAK_HBM_GBS, "traffic": counter_traffic(args.workload)},
-           "cpu_baseline": None}
+    counters = load_counters("d_product_65024x1024")
+    out = line("products of variables (the shape of the paper's Table 1), complex double: 65,024 polynomials, "
+               "each one monomial of all n = 1,024 variables (exponent 1), 1 point; dense J of 1.07 GB", 1,
+               sys_.n_monomials * K / dt, K, Wm, dt,
+               {"name": "d_product_65024x1024", "kernel_ms": ms, "algorithmic_bytes": nbytes,
+                "flops": W.flops_per_point(sys_)},
+               {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                "traffic": counter_traffic(counters)}, None)
     S.close()
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args):
-    """4096 uneven DD systems at 8 points each in one persistent launch,
-    beside the plain path (one pe_eval launch per system)."""
-    import numpy as np
-    import torch
-    from paper_1402_2626_amd import polyeval as pe
-    from paper_1402_2626_amd import synth
-    from paper_1402_2626_amd import workmodel as W
-
-    S_count, P = 4096, 8
-    ns = synth.batch_sizes(0, S_count)
-    t0 = time.perf_counter()
-    systems, dev, flops, mons = [], [], 0.0, 0
-    for i in range(S_count):
-        sy = synth.batch_system(0, i, int(ns[i]))
-        dev.append(pe.System.from_sparse(sy))
-        flops += W.flops_per_point(sy) * P
-        mons += sy.n_monomials * P
-        del sy
-        if i % 512 == 0:
-            print(f"# loaded {i} systems, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
-    B = pe.Batch(dev)
-    rng = synth.rng_for((0, 9))
-    x = torch.from_numpy(np.concatenate([synth.unit_circle_points(rng, P, int(n), 2).reshape(-1)
-                                         for n in ns])).cuda()
-    F = torch.empty(int(B.F_off[-1]) * P, dtype=torch.float64, device="cuda")
-    J = torch.empty(int(B.J_off[-1]) * P, dtype=torch.float64, device="cuda")
-    st = torch.cuda.current_stream()
-    K = max(1, min(args.steps, 5))
-    dt, ms = _time_steps(lambda: B.eval(x, P, out=(F, J), stream=st), K, 1, st)
-    # plain path: one launch per system
-    offs = [(int(B.x_off[i]) * P, int(B.F_off[i]) * P, int(B.J_off[i]) * P) for i in range(S_count)]
-    views = []
-    for i in range(S_count):
-        n = int(ns[i])
-        xo, fo, jo = offs[i]
-        views.append((x[xo:xo + P * 4 * n].view(P, 2, 2, n), F[fo:fo + P * 4 * n].view(P, 2, 2, n),
-                      J[jo:jo + P * 4 * n * n].view(P, 2, 2, n, n)))
-
-    def plain():
-        for i in range(S_count):
-            xv, fv, jv = views[i]
-            dev[i].eval(xv, out=(fv, jv), stream=st)
-    dt_plain, ms_plain = _time_steps(plain, 1, 1, st)
-    out = {"metric": "monomial eval+grad/s (complex double-double, batched uneven systems)",
-           "value": mons * K / dt, "unit": "monomials/s", "n_gpus": 1, "steps": K, "warmup": 1,
-           "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 (double-double complex)", "data": "synthetic",
-           "config": {"workload": describe("dd_batch4096"), "system_points_per_s": S_count * P * K / dt,
-                      "plain_path_ms": dt_plain * 1e3, "plain_monomials_per_s": mons / dt_plain,
-                      "monomials": mons},
-           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "traffic": None},
-           "cpu_baseline": None}
-    print(json.dumps(out), flush=True)
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-rows", type=int, default=96, help="oracle rows of the single-system workloads")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
+    ap.add_argument("--shapes", action="store_true",
+                    help="time every compiled launch shape of a single-system workload and exit")
+    ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing (single systems)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="dd_batch4096 (default, the reported line); d_n32, dd_n256, qd_n1024, "
+                         "dd_adjoint_1024x512, d_product_65024x1024, cyclic_d_n512 and cyclic_dd_n512 print "
+                         "the same kind of line for context")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path (rows of F and J would shard "
+              "across GPUs with no exchange); run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_reference:
+        import torch
+        a = torch.ones(args.copy_reference << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": a.numel() * 8, "launches": 3}), flush=True)
+        return
+    if args.workload == "dd_batch4096":
+        return bench_batch(args)
+    if args.workload == "dd_adjoint_1024x512":
+        return bench_adjoint(args)
+    if args.workload == "d_product_65024x1024":
+        return bench_product(args)
+    if args.workload in CYCLIC:
+        return bench_cyclic(args)
+    return bench_single(args)
 
 
 if __name__ == "__main__":

@@ -50,7 +50,9 @@ typedef int32_t pe_status;
 #define PE_ENOMEM (-2)        /* device or host allocation failed */
 #define PE_EUNSUPPORTED (-3)  /* valid but outside the supported sizes */
 #define PE_EDEVICE (-4)       /* a HIP runtime call failed */
-#define PE_ESINGULAR (-5)     /* a Gram-Schmidt pivot was numerically zero */
+#define PE_ESINGULAR (-5)     /* reserved: a numerically zero Gram-Schmidt pivot is
+                                 reported per point in resid_out (-1), not as
+                                 the status of the call */
 #define PE_ENONFINITE (-6)    /* non-finite values met where checked */
 
 typedef struct pe_system pe_system;
@@ -68,7 +70,7 @@ const char* pe_last_error(void);
  * monomial split of Sec. 2.1, eq. (1)).
  *   level     1, 2 or 4 (limbs per real part); all coefficients, points and
  *             outputs of this system are at this level.
- *   n_vars    number of variables n (1 <= n <= 65535).
+ *   n_vars    number of variables n (1 <= n; see the size limits below).
  *   n_polys   number of polynomials N (>= 0).
  *   poly_ptr  [N+1] int64, host: monomials of polynomial p are
  *             poly_ptr[p] .. poly_ptr[p+1]-1; poly_ptr[0] = 0, nondecreasing.
@@ -81,16 +83,23 @@ const char* pe_last_error(void);
  *   stream    stream used for the uploads (the call synchronises it).
  * Monomials with no occurrence (constants) and polynomials with no monomial
  * are allowed; duplicate monomials are kept as given (never merged).
+ * Size limits (PE_EUNSUPPORTED beyond them): n <= 2048 variables; a
+ * monomial spans at most one wavefront of 64 lanes, so it has at most
+ * 64 * segment variables: 1024 in double (segment 16), 512 in double double
+ * (segment 8), 256 in quad double (segment 4); at most 2^31 monomials and
+ * 2^32 occurrences.  (n > 65535 and monomials over 1024 variables are
+ * rejected by the validation itself.)
  * Returns PE_EINVAL for malformed input (out-of-range index, exponent < 1,
  * duplicate variable in a monomial, non-monotone offsets), PE_EUNSUPPORTED
- * for a monomial with more than 1024 variables or n > 65535, PE_ENOMEM or
- * PE_EDEVICE on allocation/copy failure.  On error *out is set to NULL. */
+ * for the size limits above, PE_ENOMEM or PE_EDEVICE on allocation/copy
+ * failure.  On error *out is set to NULL. */
 pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32_t n_polys,
                            const int64_t* poly_ptr, const int64_t* mon_ptr, const int32_t* var_idx,
                            const int32_t* exps, const double* coef, void* stream);
 
 /* Release a system and its device memory (NULL is allowed).  The caller must
- * make sure no enqueued work still uses it. */
+ * make sure no enqueued work still uses it.  PE_EINVAL (nothing released)
+ * while a batch that contains the system is alive. */
 pe_status pe_system_destroy(pe_system* sys);
 
 /* Sizes of a loaded system: info[0] = level, [1] = n, [2] = N, [3] = M,
@@ -118,8 +127,9 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[11]);
  * on `stream`, which is synchronised).  Results are bitwise reproducible for
  * a given shape; shapes differ only by rounding.  PE_EUNSUPPORTED if the
  * shape is not compiled or does not fit (LDS, column count); the previous
- * shape is then kept.  Not to be called while work using the system is
- * enqueued. */
+ * shape is then kept.  PE_EINVAL while a batch that contains the system is
+ * alive (the batch uses the packed arrays).  Not to be called while work
+ * using the system is enqueued. */
 pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_per_workgroup, void* stream);
 
 /* Evaluate F and J at P points (Sec. 2: power table, reverse-mode product
@@ -151,7 +161,8 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
  * one launch, the others a second one sized for their LDS; both are queued
  * on the caller's stream behind one counter-reset kernel.  The systems must
  * share the level and the segment length (pe_system_set_shape; PE_EINVAL
- * otherwise) and outlive the batch. */
+ * otherwise) and outlive the batch: while the batch is alive they cannot be
+ * repacked (pe_system_set_shape, pe_autotune) or destroyed (PE_EINVAL). */
 pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream);
 pe_status pe_batch_destroy(pe_batch* batch);
 
@@ -173,7 +184,9 @@ pe_status pe_batch_info(const pe_batch* batch, int64_t info[4]);
 
 /* Evaluate every system of the batch at points_per_system points each.
  * x, F, J are device arrays in the packed layout above (J may be NULL).
- * The first call with a given points_per_system may allocate workspace. */
+ * Enqueues kernels only (a counter reset and the persistent launches): no
+ * allocation, no host synchronisation, capturable in a HIP graph.  Two calls
+ * on the same batch must not overlap (they share the work-queue counters). */
 pe_status pe_batch_eval(const pe_batch* batch, int32_t points_per_system, const double* x, double* F,
                         double* J, void* stream);
 
@@ -186,7 +199,9 @@ pe_status pe_batch_eval(const pe_batch* batch, int32_t points_per_system, const 
  *              256-byte aligned, owned by the caller.
  *   resid_out  device [P][2] doubles: |F(x)|_2 before the step and
  *              |dx|_inf (leading limbs), or NULL.
- * Requires N >= n (least squares) and n + 1 <= 1024.  Enqueues kernels only
+ * Requires N >= n (least squares), n + 1 <= 1024 and the pivot column
+ * (N complex level-L numbers) within the LDS of one workgroup
+ * (PE_EUNSUPPORTED otherwise).  Enqueues kernels only
  * (no allocation, no host synchronisation): capturable in a HIP graph.  A
  * numerically zero pivot (|r_kk| <= n u_L max|r|) gives dx = 0 for that point
  * and resid_out[p][1] = -1; the call itself returns PE_OK. */

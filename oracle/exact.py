@@ -42,7 +42,7 @@ __all__ = [
     "eval_rows", "eval_columns", "eval_system", "abs_sums_rows", "rel_error",
     "max_rel_error_rows", "adjoint_exact", "adjoint_columns", "gauss_newton_step_mp",
     "system_value_at", "round_point", "speelpenning_straightforward", "plant_root",
-    "abs_sums_columns",
+    "abs_sums_columns", "abs_sums_values",
 ]
 
 # --------------------------------------------------------------------------
@@ -318,6 +318,21 @@ def abs_sums_rows(sys_, x: np.ndarray, rows: Iterable[int]):
         SF[p] = sf
         SJ[p] = sj
     return SF, SJ
+
+
+def abs_sums_values(sys_, x: np.ndarray, rows: Iterable[int]):
+    """S_F(p) = sum_t |c_t| prod |x|^d alone (float64), for rows whose
+    Jacobian normalisers are not needed: {p: S}."""
+    ax = np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+    ac = np.hypot(sys_.coef[0].sum(axis=0), sys_.coef[1].sum(axis=0))
+    SF = {}
+    for p in rows:
+        sf = 0.0
+        for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+            vs, ds = sys_.monomial(t)
+            sf += float(ac[t]) * math.prod(float(ax[v]) ** int(d) for v, d in zip(vs, ds))
+        SF[p] = sf
+    return SF
 
 
 def rel_error(got_re_limbs, got_im_limbs, exact, S: float) -> float:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -69,6 +70,16 @@ int default_seg_for(int L, const std::vector<int64_t>& mon_ptr) {
 
 int default_slots(int L) { return L == 1 ? 2304 : (L == 2 ? 1152 : 1088); }
 
+// A workgroup of G > 1 chunks adds the partial rows of sub-groups 1..G-1
+// into sub-group 0's through the G contribution regions (reused once the
+// chunks are done): (G - 1) partial rows of n columns must fit in G regions of
+// max_slots slots, and the row accumulators of a multi-chunk kernel cover at
+// most 2 * 256 columns.
+bool multi_chunk_fits(int n, int cpl, int max_slots, int G) {
+  if (G == 1) return true;
+  return cpl <= 2 && int64_t(n) * (G - 1) <= int64_t(max_slots) * G;
+}
+
 int cpl_bucket(int ncols, int T) {
   int c = (ncols + T - 1) / T;
   if (c <= 1) return 1;
@@ -117,6 +128,9 @@ struct pe_system {
   SysView view{};
   std::vector<void*> allocs;
   size_t device_bytes = 0;
+  // batches that hold a copy of this system's device view; while any is
+  // alive the system may not be repacked or destroyed
+  mutable std::atomic<int> batch_refs{0};
   // adjoint workspace
   mutable std::mutex ws_mu;
   mutable void* adj_ws = nullptr;
@@ -213,8 +227,7 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   auto fits = [&](int G) {
     if (!shape_compiled(L, seg, G)) return false;
     if (pick_table(G) < 0) return false;
-    if (G == 1) return true;
-    return pl.cpl <= 2 && H.n * (G - 1) <= pl.max_slots * G;
+    return multi_chunk_fits(H.n, pl.cpl, pl.max_slots, G);
   };
   if (force_G > 0) {
     if (!fits(force_G)) return fail(PE_EUNSUPPORTED, "this launch shape does not fit the system");
@@ -437,6 +450,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
 
 pe_status pe_system_destroy(pe_system* sys) {
   if (!sys) return PE_OK;
+  if (sys->batch_refs.load() > 0) return fail(PE_EINVAL, "the system belongs to a live batch; destroy the batch first");
   free_device(sys);
   if (sys->adj_ws) (void)hipFree(sys->adj_ws);
   delete sys;
@@ -462,6 +476,7 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[11]) {
 
 pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_per_workgroup, void* stream) {
   if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (sys->batch_refs.load() > 0) return fail(PE_EINVAL, "the system belongs to a live batch; destroy the batch first");
   if (chunks_per_workgroup < 0 || chunks_per_workgroup > 4 || chunks_per_workgroup == 3 || segment < 0)
     return fail(PE_EINVAL, "invalid launch shape");
   const int seg = segment ? segment : default_seg_for(sys->level, sys->in_mon_ptr);
@@ -765,6 +780,7 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   std::vector<int> cls_of(S, 1);
   int maxcols[2] = {1, 1};
   size_t lds2 = 0;
+  bool two_fit = shape_compiled(L, b->seg, 2);
   for (int s = 0; s < S; ++s) {
     const pe_system* y = systems[s];
     int mc = 0;
@@ -773,11 +789,15 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     cls_of[s] = c;
     maxcols[c] = std::max(maxcols[c], y->view.n);
     b->cls[c].lds = std::max(b->cls[c].lds, y->plan.lds1);
-    if (c == 0)
+    if (c == 0) {
       lds2 = std::max(lds2, lds_bytes<1>(y->view.n, y->view.tab_first, y->view.tab_last, y->view.max_slots, 2) * L);
+      two_fit = two_fit && multi_chunk_fits(y->view.n, cpl_bucket(y->view.n, kSub), y->view.max_slots, 2);
+    }
   }
   for (int c = 0; c < 2; ++c) b->cls[c].cpl = cpl_bucket(maxcols[c], kSub);
-  if (shape_compiled(L, b->seg, 2) && lds2 > 0 && lds2 <= device_lds_limit()) {
+  // two chunks per workgroup only when every system of the class fits that
+  // shape as pe_eval would run it (same rule), so rows match pe_eval bit for bit
+  if (two_fit && lds2 > 0 && lds2 <= device_lds_limit()) {
     b->cls[0].G = 2;
     b->cls[0].lds = lds2;
   }
@@ -851,12 +871,14 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     delete b;
     return fail(PE_EDEVICE, std::string("batch upload: ") + hipGetErrorString(he));
   }
+  for (const pe_system* y : b->systems) y->batch_refs.fetch_add(1);
   *out = b;
   return PE_OK;
 }
 
 pe_status pe_batch_destroy(pe_batch* b) {
   if (!b) return PE_OK;
+  for (const pe_system* y : b->systems) y->batch_refs.fetch_sub(1);
   batch_free(b);
   delete b;
   return PE_OK;
@@ -941,6 +963,7 @@ pe_status pe_batch_newton_step(const pe_batch* b, int32_t P, double* x_inout, vo
 
 pe_status pe_autotune(pe_system* sys, int32_t P, void* stream) {
   if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (sys->batch_refs.load() > 0) return fail(PE_EINVAL, "the system belongs to a live batch; destroy the batch first");
   if (P < 1) return fail(PE_EINVAL, "P must be positive");
   if (sys->view.N == 0) return PE_OK;
   hipStream_t hs = static_cast<hipStream_t>(stream);

@@ -51,6 +51,56 @@ def _cols_job(args):
     return e
 
 
+def _entries_job(args):
+    """F_p and J_{p, cols} of one row p of a system given as its own
+    one-row system ``sub`` (plain definition: F by products of powers, each
+    partial derivative by its own product)."""
+    sub, x, F_got, J_got, cols = args
+    X = O.point_from_limbs(x)
+    Fx = O.system_value_at(sub, X)[0]
+    SF = O.abs_sums_values(sub, x, [0])[0]
+    eF = O.rel_error(F_got[0], F_got[1], Fx, SF)
+    eJ = 0.0
+    if cols:
+        Jc = O.eval_columns(sub, x, cols)
+        Sc = O.abs_sums_columns(sub, x, cols)
+        for i, j in enumerate(cols):
+            eJ = max(eJ, O.rel_error(J_got[0, :, i], J_got[1, :, i], Jc[j].get(0, O.ZERO), Sc[j].get(0, 0.0)))
+    return eF, eJ
+
+
+def row_subsystem(sys_, rows):
+    """The polynomials `rows` of a system as a system of their own (same
+    variables), for oracle checks of sampled rows of a large system."""
+    from paper_1402_2626_amd.synth import PolySystem
+    mons = [list(range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1]))) for p in rows]
+    poly_ptr = np.cumsum([0] + [len(m) for m in mons]).astype(np.int64)
+    flat = [t for m in mons for t in m]
+    mon_ptr = np.cumsum([0] + [int(sys_.mon_ptr[t + 1] - sys_.mon_ptr[t]) for t in flat]).astype(np.int64)
+    occ = (np.concatenate([np.arange(sys_.mon_ptr[t], sys_.mon_ptr[t + 1]) for t in flat]).astype(np.int64)
+           if flat else np.zeros(0, np.int64))
+    return PolySystem(level=sys_.level, n_vars=sys_.n_vars, poly_ptr=poly_ptr, mon_ptr=mon_ptr,
+                      var_idx=np.ascontiguousarray(sys_.var_idx[occ]), exps=np.ascontiguousarray(sys_.exps[occ]),
+                      coef=np.ascontiguousarray(sys_.coef[:, :, flat]), name=sys_.name + "_rows")
+
+
+def max_errors_entries(sys_, x, F, J, picks, parallel: bool = True):
+    """Largest metric over sampled entries: ``picks`` maps a row p to the
+    columns of J to check there (F_p is always checked).  x: [2, L, n];
+    F: [2, L, N]; J: [2, L, N, n] (numpy)."""
+    jobs = []
+    for p, cols in picks.items():
+        cols = list(cols)
+        sub = row_subsystem(sys_, [p])
+        jobs.append((sub, x, F[:, :, p], J[:, :, p, cols] if cols else None, cols))
+    if parallel and len(jobs) > 1:
+        with _pool(min(workers(), len(jobs))) as pool:
+            res = pool.map(_entries_job, jobs)
+    else:
+        res = [_entries_job(j) for j in jobs]
+    return max(r[0] for r in res), max(r[1] for r in res)
+
+
 def _pool(n):
     return mp.get_context("spawn").Pool(n)
 

@@ -434,8 +434,9 @@ def pin_abs_sums_positive() -> bool:
     F, J = OE.eval_rows(sys_, x, range(5))
     SF, SJ = OE.abs_sums_rows(sys_, x, range(5))
     Sc = OE.abs_sums_columns(sys_, x, range(7))
+    Sv = OE.abs_sums_values(sys_, x, range(5))
     for p in range(5):
-        if SF[p] != OE.cdy_abs_float(F[p]):
+        if SF[p] != OE.cdy_abs_float(F[p]) or Sv[p] != SF[p]:
             return False
         if set(SJ[p]) != set(J[p]):
             return False

@@ -165,3 +165,36 @@ def test_adjoint_finite_differences(pe):
     lhs = (acc[0], 0, acc[2])  # Re<J^H v, w>, exact from the GPU limbs
     diff = O.cdy_abs_float(O.cdy_add(lhs, O.cdy_neg(fd)))
     assert diff <= 1e-35 * max(1.0, O.cdy_abs_float(fd)), diff
+
+
+def test_autograd_dd_1024x512(pe):
+    """PolyEval.apply at the adjoint workload's shape (N = 1024, n = 512, 512
+    monomials of k = 24, 64 points): forward F on sampled rows and the
+    backward J^H v on sampled columns at two points against the oracle."""
+    import torch
+    from paper_1402_2626_amd.autograd import PolyEval
+
+    sys_, x = synth.workload("dd_adjoint_1024x512")
+    P = x.shape[0]
+    v = synth.adjoint_vectors(0, P, sys_.n_polys, sys_.level)
+    S = pe.System.from_sparse(sys_)
+    xt = U.to_device(x).requires_grad_(True)
+    U.flush("autograd 1024x512: forward and backward")
+    F = PolyEval.apply(xt, S)
+    F.backward(U.to_device(v))
+    torch.cuda.synchronize()
+    g = xt.grad.cpu().numpy()
+    Fn = F.detach().cpu().numpy()
+    S.close()
+    tol = U.tolerance(sys_)
+    cols = [3, 256, 510]
+    for pt in (1, 62):
+        U.flush(f"autograd 1024x512: oracle at point {pt}")
+        eF, _ = U.max_errors_entries(sys_, x[pt], Fn[pt], np.zeros((2, 2, sys_.n_polys, 1)),
+                                     {0: [], 511: [], 1023: []})
+        assert eF <= tol, (pt, eF)
+        scale = _adjoint_scale(sys_, x[pt], v[pt], cols)
+        exact = O.adjoint_columns(sys_, x[pt], v[pt], cols)
+        for j in cols:
+            e = O.rel_error(g[pt, 0, :, j], g[pt, 1, :, j], exact[j], scale[j])
+            assert e <= tol, (pt, j, e)

@@ -53,6 +53,12 @@ def test_batch_uneven_matches_single_and_oracle(pe):
     F, J = B.eval(xflat, P)
     torch.cuda.synchronize()
     F, J = F.cpu().numpy(), J.cpu().numpy()
+    # F only
+    Fo, Jo = B.eval(xflat, P, want_J=False)
+    torch.cuda.synchronize()
+    assert Jo is None
+    Fo = Fo.cpu().numpy()
+    B.close()  # the systems may be repacked once no batch holds them
     for i in range(S_count):
         n = int(ns[i])
         Fi = _unpack(F, B.F_off, i, (P, 2, 2, n), P)
@@ -70,16 +76,111 @@ def test_batch_uneven_matches_single_and_oracle(pe):
         for pt in (0, 7):
             eF, eJ = U.max_errors_rows(systems[i], xs[i][pt], Fi[pt], Ji[pt], [0, n - 1], parallel=False)
             assert eF <= tol and eJ <= tol, (i, pt, eF, eJ)
-    # F only
-    Fo, Jo = B.eval(xflat, P, want_J=False)
-    torch.cuda.synchronize()
-    assert Jo is None
-    Fo = Fo.cpu().numpy()
     for i in (2, 9):
         n = int(ns[i])
         eF, _ = U.max_errors_rows(systems[i], xs[i][3], _unpack(Fo, B.F_off, i, (P, 2, 2, n), P)[3], None,
                                   [0, 1], parallel=False)
         assert eF <= U.tolerance(systems[i])
+    for d in dev:
+        d.close()
+
+
+def test_batch_refuses_repack_while_alive(pe):
+    """A system held by a live batch cannot be repacked, tuned or destroyed
+    (the batch keeps its device arrays); after the batch is destroyed it can."""
+    sys_ = synth.batch_system(0, 3, 64)
+    S = pe.System.from_sparse(sys_)
+    B = pe.Batch([S, S])
+    for call in (lambda: S.set_shape(1, segment=4), lambda: S.autotune(1)):
+        with pytest.raises(pe.PolyevalError) as e:
+            call()
+        assert e.value.status == pe.PE_EINVAL and "live batch" in str(e.value)
+    assert pe._lib.pe_system_destroy(S.handle) == pe.PE_EINVAL
+    B.close()
+    S.set_shape(1, segment=4)
+    S.close()
+
+
+def test_batch_wide_rows_of_small_monomials(pe):
+    """A dense linear system of 1,024 variables (monomials of one variable,
+    four chunks per row, slot regions of 257 slots) batched with a system of
+    multi-chunk rows: the batch must not take two chunks per workgroup for
+    rows too wide for the slot regions; rows against the oracle and equal to
+    pe_eval."""
+    import torch
+    rng = synth.rng_for(601)
+    n = 1024
+    polys = [[(0, [(j, 1)]) for j in range(n)] for _ in range(5)]
+    wide = synth.from_monomial_lists(2, n, polys, coef_limbs=synth.unit_circle(rng, 5 * n, 2), name="dense_linear")
+    other = synth.batch_system(0, 11, 128)
+    systems = [wide, other]
+    dev = [pe.System.from_sparse(s) for s in systems]
+    dev[1].set_shape(0, segment=dev[0].info()["segment"])
+    B = pe.Batch(dev)
+    P = 2
+    xs = [synth.unit_circle_points(synth.rng_for((602, i)), P, s.n_vars, 2) for i, s in enumerate(systems)]
+    F, J = B.eval(U.to_device(_pack_points(B, xs, P)), P)
+    torch.cuda.synchronize()
+    F, J = F.cpu().numpy(), J.cpu().numpy()
+    G = B.info()["chunks_per_workgroup"]
+    B.close()
+    for i, s in enumerate(systems):
+        Fi = _unpack(F, B.F_off, i, (P, 2, 2, s.n_polys), P)
+        Ji = _unpack(J, B.J_off, i, (P, 2, 2, s.n_polys, s.n_vars), P)
+        tol = U.tolerance(s)
+        for pt in range(P):
+            eF, eJ = U.max_errors_rows(s, xs[i][pt], Fi[pt], Ji[pt], [0, s.n_polys - 1], parallel=False)
+            assert eF <= tol and eJ <= tol, (i, pt, eF, eJ, G)
+        if i == 0:
+            F1, J1 = dev[i].eval(U.to_device(xs[i]))
+            torch.cuda.synchronize()
+            assert np.array_equal(F1.cpu().numpy(), Fi) and np.array_equal(J1.cpu().numpy(), Ji)
+    for d in dev:
+        d.close()
+
+
+def test_batch_4096_full_size(pe):
+    """The uneven DD batch at full size: 4,096 systems (n = N = m uniform in
+    {32, 64, 128, 256}, k = min(16, n/4), exponents 1..3) at 8 points each,
+    one call.  Two systems of each size: first and last rows at the first and
+    last point against the oracle; 64 systems (16 of each size) equal to
+    pe_eval on their own, bit for bit, on the device."""
+    import torch
+    S_count, P = 4096, 8
+    ns = synth.batch_sizes(0, S_count)
+    U.flush("batch 4096: loading systems")
+    dev = [pe.System.from_sparse(synth.batch_system(0, i, int(ns[i]))) for i in range(S_count)]
+    B = pe.Batch(dev)
+    rng = synth.rng_for((0, 9))
+    xs_host = [synth.unit_circle_points(rng, P, int(n), 2) for n in ns]
+    x = U.to_device(np.concatenate([a.reshape(-1) for a in xs_host]))
+    U.flush("batch 4096: persistent launch")
+    F, J = B.eval(x, P)
+    torch.cuda.synchronize()
+    G = B.info()["chunks_per_workgroup"]
+    by_n = {int(n): [i for i in range(S_count) if int(ns[i]) == int(n)] for n in (32, 64, 128, 256)}
+    checked = 0
+    for n, idx in by_n.items():
+        for i in (idx[0], idx[-1]):
+            sys_ = synth.batch_system(0, i, n)
+            a, b = int(B.F_off[i]) * P, int(B.J_off[i]) * P
+            Fi = F[a:a + P * 4 * n].view(P, 2, 2, n).cpu().numpy()
+            Ji = J[b:b + P * 4 * n * n].view(P, 2, 2, n, n).cpu().numpy()
+            tol = U.tolerance(sys_)
+            for pt in (0, P - 1):
+                U.flush(f"batch 4096: oracle system {i} (n = {n}) point {pt}")
+                eF, eJ = U.max_errors_rows(sys_, xs_host[i][pt], Fi[pt], Ji[pt], [0, n - 1], parallel=True)
+                assert eF <= tol and eJ <= tol, (i, n, pt, eF, eJ)
+                checked += 1
+        for i in idx[:: max(1, len(idx) // 16)][:16]:
+            info = dev[i].info()
+            assert info["chunks_per_workgroup"] in (1, G), (i, info, G)
+            a, f, b = int(B.x_off[i]) * P, int(B.F_off[i]) * P, int(B.J_off[i]) * P
+            F1, J1 = dev[i].eval(x[a:a + P * 4 * n].view(P, 2, 2, n))
+            assert torch.equal(F1.reshape(-1), F[f:f + P * 4 * n]), i
+            assert torch.equal(J1.reshape(-1), J[b:b + P * 4 * n * n]), i
+    assert checked == 16
+    del F, J
     B.close()
     for d in dev:
         d.close()

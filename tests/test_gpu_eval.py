@@ -335,20 +335,6 @@ def test_default_segment_follows_monomial_size(pe):
         S.close()
 
 
-def _row_subsystem(sys_, rows):
-    """The polynomials `rows` of a system as a system of their own (same
-    variables), for oracle checks of sampled rows of a large system."""
-    from paper_1402_2626_amd.synth import PolySystem
-    mons = [list(range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1]))) for p in rows]
-    poly_ptr = np.cumsum([0] + [len(m) for m in mons]).astype(np.int64)
-    flat = [t for m in mons for t in m]
-    mon_ptr = np.cumsum([0] + [int(sys_.mon_ptr[t + 1] - sys_.mon_ptr[t]) for t in flat]).astype(np.int64)
-    occ = np.concatenate([np.arange(sys_.mon_ptr[t], sys_.mon_ptr[t + 1]) for t in flat]).astype(np.int64)
-    return PolySystem(level=sys_.level, n_vars=sys_.n_vars, poly_ptr=poly_ptr, mon_ptr=mon_ptr,
-                      var_idx=np.ascontiguousarray(sys_.var_idx[occ]), exps=np.ascontiguousarray(sys_.exps[occ]),
-                      coef=np.ascontiguousarray(sys_.coef[:, :, flat]), name=sys_.name + "_rows")
-
-
 def test_product_table1_shape(pe):
     """The Table-1 shape in complex double (65,024 polynomials, each the
     product of all 1,024 variables) at full size: three sampled rows against
@@ -364,7 +350,7 @@ def test_product_table1_shape(pe):
     S.close()
     tol = U.tolerance(sys_)
     rows = [0, 32511, sys_.n_polys - 1]
-    sub = _row_subsystem(sys_, rows)
+    sub = U.row_subsystem(sys_, rows)
     Fs = F[:, :, :, rows].cpu().numpy()[0]
     Js = J[:, :, :, rows, :].cpu().numpy()[0]
     eF, eJ = U.max_errors_rows(sub, x[0], Fs, Js, range(len(rows)), parallel=True)
@@ -396,3 +382,122 @@ def test_cyclic_512_closed_forms(pe, L):
     want_J = np.repeat(np.arange(1, n + 1, dtype=float)[:, None], n, axis=1)
     want_J[-1] = 1.0
     assert np.array_equal(J[0, 0, 0], want_J) and np.all(J[0, 1] == 0) and np.all(J[0, 0, 1:] == 0)
+
+
+def _cyclic_roots_of_unity(n, rows, prec=200):
+    """Cyclic n-roots (eq. (5)) at x_k = w^k, w = e^(2 pi i / n), in closed
+    form: row r < n - 1 (monomials of d = r + 1 cyclically consecutive
+    variables) has F_r = w^(d(d-1)/2) sum_j w^(dj) = 0 and
+    J_{r,m} = w^((d-1)m + d(d-1)/2) sum_{t<d} w^(-dt) (a geometric sum); the
+    last row x_0 ... x_(n-1) - 1 has F = (-1)^(n-1) - 1 and
+    J_{n-1,m} = (-1)^(n-1) w^(-m).  Returns (x limbs helper, {r: F}, {r: [J]})
+    as mpmath values."""
+    import mpmath
+    with mpmath.workprec(prec):
+        W = [mpmath.expjpi(mpmath.mpf(2 * k) / n) for k in range(n)]
+        Fr, Jr = {}, {}
+        for r in rows:
+            if r == n - 1:
+                sgn = -1 if (n - 1) % 2 else 1
+                Fr[r] = mpmath.mpc(sgn - 1)
+                Jr[r] = [sgn * W[(-m) % n] for m in range(n)]
+                continue
+            d = r + 1
+            geo = mpmath.fsum(W[(-d * t) % n] for t in range(d))
+            Fr[r] = mpmath.mpc(0)
+            Jr[r] = [W[((d - 1) * m + d * (d - 1) // 2) % n] * geo for m in range(n)]
+    return W, Fr, Jr
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_cyclic_512_roots_of_unity(pe, L):
+    """Cyclic 512-roots at x_k = w^k rounded to the level: F and sampled full
+    rows of J (the shortest, middle, longest and last rows) against the
+    closed forms; normaliser S = number of terms (unit moduli)."""
+    import mpmath
+    import torch
+    n = 512
+    sys_ = synth.cyclic_roots_system(n, L)
+    rows = [0, 1, 2, 7, 63, 127, 255, 256, 383, 449, 500, 507, 508, 509, 510, 511]
+    W, Fr, Jr = _cyclic_roots_of_unity(n, rows)
+    x = np.zeros((1, 2, L, n))
+    with mpmath.workprec(200):
+        for k in range(n):
+            for part, val in ((0, W[k].real), (1, W[k].imag)):
+                rem = val
+                for l in range(L):
+                    f = float(rem)
+                    x[0, part, l, k] = f
+                    rem -= f
+    S = pe.System.from_sparse(sys_)
+    F, J = S.eval(U.to_device(x))
+    torch.cuda.synchronize()
+    S.close()
+    F, J = F.cpu().numpy()[0], J.cpu().numpy()[0]
+    tol = U.tolerance(sys_)
+    # F of every row: zero up to rounding, normalised by n terms of modulus 1
+    with mpmath.workprec(200):
+        def val(a):
+            return mpmath.mpc(mpmath.fsum(mpmath.mpf(float(v)) for v in a[0]),
+                              mpmath.fsum(mpmath.mpf(float(v)) for v in a[1]))
+        eF = max(float(abs(val(F[:, :, r]))) / n for r in range(n - 1))
+        eF = max(eF, float(abs(val(F[:, :, n - 1]) - Fr[n - 1])) / 2)
+        eJ = 0.0
+        for r in rows:
+            scale = 1.0 if r == n - 1 else float(r + 1)
+            for m in range(n):
+                eJ = max(eJ, float(abs(val(J[:, :, r, m]) - Jr[r][m])) / scale)
+    U.flush(f"cyclic512 roots of unity L={L}: eF={eF:.2e} eJ={eJ:.2e} tol={tol:.1e}")
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_cyclic_512_random_point(pe, L):
+    """Cyclic 512-roots at a random unit-circle point (the bench workload):
+    18 sampled rows against the oracle -- full rows of J where the
+    monomials are short, F and four columns on the long rows (up to the
+    longest, 511 variables, and the last, 512)."""
+    import torch
+    n = 512
+    sys_ = synth.cyclic_roots_system(n, L)
+    x = synth.unit_circle_points(synth.rng_for((0, 1)), 1, n, L)
+    S = pe.System.from_sparse(sys_)
+    F, J = S.eval(U.to_device(x))
+    torch.cuda.synchronize()
+    S.close()
+    F, J = F.cpu().numpy()[0], J.cpu().numpy()[0]
+    picks = {r: range(n) for r in (0, 1, 2, 5, 15, 31)}
+    for r in (63, 127, 200, 255, 256, 320, 400, 480, 509, 510, 511):
+        picks[r] = [0, r // 2, (r + 7) % n, n - 1]
+    picks[300] = list(range(0, n, 64))
+    U.flush(f"cyclic512 random point L={L}: oracle over {len(picks)} rows")
+    eF, eJ = U.max_errors_entries(sys_, x[0], F, J, picks)
+    tol = U.tolerance(sys_)
+    U.flush(f"cyclic512 random point L={L}: eF={eF:.2e} eJ={eJ:.2e} tol={tol:.1e}")
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("level, n, k, words", [
+    (2, 2049, 3, "2048 variables"),
+    (1, 2049, 3, "2048 variables"),
+    (2, 600, 513, "too large for the segment"),
+    (4, 300, 257, "too large for the segment"),
+])
+def test_size_limits_are_reported(pe, level, n, k, words):
+    """The size limits of the header: more than 2048 variables, a double-double
+    monomial of 513 variables and a quad-double monomial of 257 are refused
+    with PE_EUNSUPPORTED through the C ABI, and nothing is created."""
+    import ctypes
+    sys_ = synth.random_system(5, level, n_vars=n, n_polys=2, m=2, k=k, exp_lo=1, exp_hi=2)
+    h = ctypes.c_void_p()
+    arrs = [np.ascontiguousarray(a) for a in (sys_.poly_ptr, sys_.mon_ptr, sys_.var_idx, sys_.exps, sys_.coef)]
+    st = pe._lib.pe_system_create(ctypes.byref(h), level, n, sys_.n_polys, *[a.ctypes.data for a in arrs], None)
+    assert st == pe.PE_EUNSUPPORTED, st
+    assert words in pe._lib.pe_last_error().decode()
+    assert not h.value
+    # the largest sizes within the limits load and evaluate
+    kmax = {1: 1024, 2: 512, 4: 256}[level]
+    ok = synth.random_system(6, level, n_vars=min(n, 2048), n_polys=1, m=1, k=min(k, kmax, min(n, 2048)),
+                             exp_lo=1, exp_hi=1)
+    S = pe.System.from_sparse(ok)
+    S.close()
