@@ -199,9 +199,10 @@ pe_status pe_batch_eval(const pe_batch* batch, int32_t points_per_system, const 
  *              256-byte aligned, owned by the caller.
  *   resid_out  device [P][2] doubles: |F(x)|_2 before the step and
  *              |dx|_inf (leading limbs), or NULL.
- * Requires N >= n (least squares), n + 1 <= 1024 and the pivot column
- * (N complex level-L numbers) within the LDS of one workgroup
- * (PE_EUNSUPPORTED otherwise).  Enqueues kernels only
+ * Systems with fewer than 128 variables are solved by one workgroup per
+ * point; larger ones by the column-parallel solve of pe_lstsq below.
+ * Requires N >= n (least squares), N <= 4096 for the column-parallel solve
+ * and at most 65535 points (PE_EUNSUPPORTED otherwise).  Enqueues kernels only
  * (no allocation, no host synchronisation): capturable in a HIP graph.  A
  * numerically zero pivot (|r_kk| <= n u_L max|r|) gives dx = 0 for that point
  * and resid_out[p][1] = -1; the call itself returns PE_OK. */
@@ -210,10 +211,36 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
                          double* resid_out, void* stream);
 
 /* The same for every system of a batch, x in the packed batch layout;
- * resid_out is [S][P][2]. */
+ * resid_out is [S][P][2].  Every system is solved by one workgroup per point:
+ * n + 1 <= 1024 and the largest pivot column within one workgroup's LDS. */
 size_t pe_batch_newton_workspace_bytes(const pe_batch* batch, int32_t P);
 pe_status pe_batch_newton_step(const pe_batch* batch, int32_t P, double* x_inout, void* workspace,
                                double* resid_out, void* stream);
+
+/* ------------------------------------------------------------------ least squares
+ * Solve A x = b in the least-squares sense by modified Gram-Schmidt on the
+ * augmented matrix [A b] = [Q q][R y; 0 z] (Sec. 3, Fig. 4, eq. (2)):
+ * right-looking, one workgroup per column; the inner products in rounds of
+ * tiled partial sums (eq. (3)); the pivot columns normalised only when
+ * needed (delayed normalisation: r_kj = a_k^H a_j / |a_k| and the update
+ * divides by |a_k|^2); then the back substitution R x = y in stages of
+ * blocks of 256 rows (eq. (4)).
+ *   level      1, 2 or 4.  P points (independent problems), 0 <= P <= 65535.
+ *   N, n       rows and unknowns: 1 <= n <= N <= 4096.
+ *   Ab         device [P][2][L][N][n+1] row-major, column n = b; read only.
+ *   x          device [P][2][L][n], the solution (written).
+ *   resid_out  device [P][2] or NULL: |b|_2 (leading limbs) and |x|_inf, or
+ *              -1 when a pivot was numerically zero (|r_kk| <= n u_L
+ *              max |r_ii|; x is then 0).
+ *   R_out      device [P][2][L][n][n+1] or NULL: R (upper triangular, real
+ *              positive diagonal, zeros below) with y = Q^H b as column n.
+ *   Q_out      device [P][2][L][N][n] or NULL: the orthonormal columns.
+ *   workspace  device, pe_lstsq_workspace_bytes(level, P, N, n) bytes,
+ *              256-byte aligned, caller-owned.
+ * Enqueues kernels only (no allocation, no synchronisation): capturable. */
+size_t pe_lstsq_workspace_bytes(int32_t level, int32_t P, int32_t N, int32_t n);
+pe_status pe_lstsq(int32_t level, int32_t P, int32_t N, int32_t n, const double* Ab, double* x, double* resid_out,
+                   double* R_out, double* Q_out, void* workspace, void* stream);
 
 /* ------------------------------------------------------------------ tuning
  * Time the candidate launch shapes for this system at P points on the

@@ -42,7 +42,7 @@ __all__ = [
     "eval_rows", "eval_columns", "eval_system", "abs_sums_rows", "rel_error",
     "max_rel_error_rows", "adjoint_exact", "adjoint_columns", "gauss_newton_step_mp",
     "system_value_at", "round_point", "speelpenning_straightforward", "plant_root",
-    "abs_sums_columns", "abs_sums_values",
+    "abs_sums_columns", "abs_sums_values", "lstsq_limbs",
 ]
 
 # --------------------------------------------------------------------------
@@ -429,13 +429,42 @@ def gauss_newton_step_mp(sys_, X_exact, prec: int = 512):
             for j, val in J[p].items():
                 A[p, j] = mpc(val)
             b[p] = -mpc(F[p])
-        # least squares: A = QR (Householder, mpmath.qr), then R dx = Q^H b
-        Q, Rm = mpmath.qr(A, mode="skinny")
-        dx = mpmath.lu_solve(Rm, Q.H * b)
+        dx = _lstsq_householder(A, b)
         fnorm = float(mpmath.norm(b, 2))
         dinf = float(max(abs(dx[j]) for j in range(n))) if n else 0.0
         newX = [_mpc_to_cdy(mpc(X_exact[j]) + dx[j]) for j in range(n)]
     return newX, (fnorm, dinf)
+
+
+def _lstsq_householder(A, b):
+    """Least-squares solution of A x = b at mpmath's working precision: A = QR
+    by Householder reflections (``mpmath.qr``), then R x = Q^H b."""
+    import mpmath
+    Q, Rm = mpmath.qr(A, mode="skinny")
+    return mpmath.lu_solve(Rm, Q.H * b)
+
+
+def lstsq_limbs(Ab: np.ndarray, prec: int = 400):
+    """Least-squares solution of A x = b for level-L limbs Ab[2, L, N, n + 1]
+    (column n is b), each entry converted exactly; Householder QR at ``prec``
+    bits (the solve of the Gauss-Newton step above).  Returns the n components
+    as exact dyadic values."""
+    import mpmath
+    N, n = Ab.shape[2], Ab.shape[3] - 1
+    with mpmath.workprec(prec):
+        def mpc(a):
+            return mpmath.mpc(mpmath.ldexp(a[0], a[2]), mpmath.ldexp(a[1], a[2]))
+        A = mpmath.matrix(N, n)
+        b = mpmath.matrix(N, 1)
+        for i in range(N):
+            for j in range(n + 1):
+                v = mpc(cdy_from_limbs(Ab[0, :, i, j], Ab[1, :, i, j]))
+                if j < n:
+                    A[i, j] = v
+                else:
+                    b[i] = v
+        x = _lstsq_householder(A, b)
+        return [_mpc_to_cdy(x[j]) for j in range(n)]
 
 
 def _mpf_to_dy(v):

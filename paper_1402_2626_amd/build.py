@@ -24,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PE_OFFLOAD_ARCH", "gfx950")
 
 LEVELS = (1, 2, 4)
-KINDS = (0, 1, 2, 3)  # rows, adjoint, batch, Gauss-Newton
+KINDS = (0, 1, 2, 3, 4)  # rows, adjoint, batch, Gauss-Newton, least squares
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

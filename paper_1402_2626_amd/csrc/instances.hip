@@ -1,11 +1,12 @@
 // Instances of the kernel launchers of launch.hpp for one level and one kind,
 // chosen at compile time: PE_LEVEL (1, 2 or 4) and PE_KIND (0 rows, 1 adjoint,
-// 2 batch, 3 Gauss-Newton).  The build compiles this file once per pair.
+// 2 batch, 3 Gauss-Newton in one workgroup, 4 column-parallel least squares).
+// The build compiles this file once per pair.
 #define PE_LAUNCH_DEFINITIONS
 #include "launch.hpp"
 
 #if !defined(PE_LEVEL) || !defined(PE_KIND)
-#error "compile with -DPE_LEVEL=<1|2|4> -DPE_KIND=<0..3>"
+#error "compile with -DPE_LEVEL=<1|2|4> -DPE_KIND=<0..4>"
 #endif
 
 namespace pe {
@@ -22,6 +23,9 @@ template hipError_t launch_mgs<PE_LEVEL>(int, int, int, double*, int64_t, double
                                          double*, hipStream_t);
 template hipError_t launch_mgs_batch<PE_LEVEL>(int, int, int, const BatchNewtonDesc*, const int*, double*, double*,
                                                double*, double*, double*, hipStream_t);
+#elif PE_KIND == 4
+template hipError_t launch_lstsq<PE_LEVEL>(const LsLayout&, void*, const double*, int64_t, int64_t, int64_t, double*,
+                                           int64_t, int, double*, double*, double*, hipStream_t);
 #endif
 
 }  // namespace pe

@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "eval_kernels.hpp"
+#include "lstsq_kernels.hpp"
 #include "newton_kernels.hpp"
 
 namespace pe {
@@ -70,6 +71,19 @@ hipError_t launch_mgs(int P, int N, int n, double* W, int64_t w_pt, double* R, i
 template <int L>
 hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc, const int* order, double* W,
                             double* R, double* Y, double* x, double* resid, hipStream_t st);
+
+// Column-parallel least-squares solve of the augmented matrices [A b] given
+// row-major at A (row stride ld, component plane stride a_plane, point stride
+// a_pt; see lstsq_kernels.hpp), writing x (x_pt per point; add = 1 adds the
+// solution to x, the Newton update), resid[P][2] and optionally R and Q.
+// PE panel of pivots per launch: kLsPanel.
+constexpr int kLsPanel = 32;
+constexpr int kLsMaxRows = 4096;  // N limit of the column-parallel solve
+
+template <int L>
+hipError_t launch_lstsq(const LsLayout& lo, void* ws, const double* A, int64_t ld, int64_t a_plane, int64_t a_pt,
+                        double* x, int64_t x_pt, int add, double* resid, double* Rout, double* Qout,
+                        hipStream_t st);
 
 #ifdef PE_LAUNCH_DEFINITIONS
 
@@ -238,6 +252,84 @@ hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc,
   hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(S) * P)), dim3(kMgsThreads), lds, st, desc, order, P, W, R, Y, x,
                      resid);
   return hipGetLastError();
+}
+
+template <int L, int T, int EPT>
+hipError_t ls_sweep(const LsView& V, int P, hipStream_t st) {
+  const int n = V.n;
+  auto apply = [&](int k0, int k1, int j0, int j1) -> hipError_t {
+    if (j1 <= j0) return hipSuccess;
+    hipLaunchKernelGGL((ls_apply_kernel<L, T, EPT>), dim3(unsigned(int64_t(P) * (j1 - j0))), dim3(T), 0, st, V, k0,
+                       k1, j0, j1);
+    return hipGetLastError();
+  };
+  hipError_t e = apply(0, 0, 0, 1);  // the norm of column 0
+  for (int k0 = 0; k0 < n && e == hipSuccess; k0 += kLsPanel) {
+    const int k1 = std::min(k0 + kLsPanel, n);
+    for (int c = k0; c + 1 < k1 && e == hipSuccess; ++c) e = apply(c, c + 1, c + 1, k1);
+    if (e == hipSuccess) e = apply(k0, k1, k1, n + 1);
+  }
+  return e;
+}
+
+// threads and rows per thread of the sweep: T * EPT >= N, registers for the
+// column and one pivot within about 128 VGPRs
+template <int L>
+hipError_t ls_sweep_for(const LsView& V, int P, hipStream_t st) {
+  const int N = V.N;
+  if constexpr (L <= 2) {
+    if (N <= 256) return ls_sweep<L, 256, 1>(V, P, st);
+    if (N <= 512) return ls_sweep<L, 256, 2>(V, P, st);
+    if (N <= 1024) return ls_sweep<L, 256, 4>(V, P, st);
+    if (N <= 2048) return ls_sweep<L, 256, 8>(V, P, st);
+    if (N <= 4096) return ls_sweep<L, 512, 8>(V, P, st);
+  } else {
+    if (N <= 256) return ls_sweep<L, 256, 1>(V, P, st);
+    if (N <= 512) return ls_sweep<L, 256, 2>(V, P, st);
+    if (N <= 1024) return ls_sweep<L, 256, 4>(V, P, st);
+    if (N <= 2048) return ls_sweep<L, 256, 8>(V, P, st);
+    if (N <= 4096) return ls_sweep<L, 256, 16>(V, P, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+hipError_t launch_lstsq(const LsLayout& lo, void* ws, const double* A, int64_t ld, int64_t a_plane, int64_t a_pt,
+                        double* x, int64_t x_pt, int add, double* resid, double* Rout, double* Qout,
+                        hipStream_t st) {
+  const LsView V = ls_view(lo, ws);
+  const int P = lo.P, N = lo.N, n = lo.n;
+  const int tiles = ((n + 1 + 63) / 64) * ((N + 63) / 64);
+  hipLaunchKernelGGL(ls_copy_in_kernel<L>, dim3(unsigned(tiles), unsigned(2 * L), unsigned(P)), dim3(256), 0, st, V,
+                     A, ld, a_plane, a_pt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (resid) {
+    hipLaunchKernelGGL(ls_bnorm_kernel<L>, dim3(unsigned(P)), dim3(256), 0, st, V, resid);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = ls_sweep_for<L>(V, P, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(ls_init_y_kernel<L>, dim3(unsigned((n + 255) / 256), unsigned(P)), dim3(256), 0, st, V);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int end = n; end > 0; end -= kBs) {
+    const int s = std::max(0, end - kBs);
+    hipLaunchKernelGGL(ls_backsub_diag_kernel<L>, dim3(unsigned(P)), dim3(kBs), 0, st, V, s, end);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (s > 0) {
+      hipLaunchKernelGGL(ls_backsub_update_kernel<L>, dim3(unsigned((s + kBs - 1) / kBs), unsigned(P)), dim3(kBs), 0,
+                         st, V, s, end);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(ls_finish_kernel<L>, dim3(unsigned(P)), dim3(256), 0, st, V, x, x_pt, add, resid);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (Rout || Qout) {
+    const int64_t cnt = std::max(int64_t(N) * n, int64_t(n) * (n + 1));
+    hipLaunchKernelGGL(ls_export_kernel<L>, dim3(unsigned((cnt + 255) / 256), unsigned(P)), dim3(256), 0, st, V, Rout,
+                       Qout);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 #endif  // PE_LAUNCH_DEFINITIONS

@@ -603,15 +603,35 @@ hipError_t dispatch_mgs(int L, int P, int N, int n, double* W, const NewtonLayou
   return hipErrorInvalidValue;
 }
 
+// The one-workgroup solve (mgs_solve_kernel) for small systems; the
+// column-parallel one (launch_lstsq) once a system has 128 variables or more,
+// or when the one-workgroup kernel's limits (n + 1 <= 1024, the pivot column
+// in LDS) do not hold.
+bool newton_column_parallel(const pe_system* sys) {
+  const int n = sys->view.n, N = sys->view.N, L = sys->level;
+  const size_t lds = L == 1 ? mgs_lds_bytes<1>(N) : (L == 2 ? mgs_lds_bytes<2>(N) : mgs_lds_bytes<4>(N));
+  return n >= 128 || n + 1 > 1024 || lds > device_lds_limit();
+}
+
 pe_status newton_check(const pe_system* sys, int P) {
   const int n = sys->view.n, N = sys->view.N;
-  if (N < n) return fail(PE_EUNSUPPORTED, "Gauss-Newton needs at least as many polynomials as variables");
-  if (n + 1 > 1024) return fail(PE_EUNSUPPORTED, "Gauss-Newton supports n + 1 <= 1024");
-  const int L = sys->level;
-  const size_t lds = L == 1 ? mgs_lds_bytes<1>(N) : (L == 2 ? mgs_lds_bytes<2>(N) : mgs_lds_bytes<4>(N));
-  if (lds > device_lds_limit()) return fail(PE_EUNSUPPORTED, "too many polynomials for the LDS pivot column");
   if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  if (N < n) return fail(PE_EUNSUPPORTED, "Gauss-Newton needs at least as many polynomials as variables");
+  if (newton_column_parallel(sys) && N > kLsMaxRows)
+    return fail(PE_EUNSUPPORTED, "the least-squares solve supports at most 4096 polynomials");
+  if (P > 65535) return fail(PE_EUNSUPPORTED, "at most 65535 points per call");
   return PE_OK;
+}
+
+hipError_t dispatch_lstsq(int L, const LsLayout& lo, void* ws, const double* A, int64_t ld, int64_t a_plane,
+                          int64_t a_pt, double* x, int64_t x_pt, int add, double* resid, double* Rout, double* Qout,
+                          hipStream_t st) {
+  switch (L) {
+    case 1: return launch_lstsq<1>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
+    case 2: return launch_lstsq<2>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
+    case 4: return launch_lstsq<4>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -620,7 +640,10 @@ extern "C" {
 
 size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P) {
   if (!sys || P < 0) return 0;
-  return newton_layout(sys->level, sys->view.N, sys->view.n, P).total;
+  const int L = sys->level, N = sys->view.N, n = sys->view.n;
+  if (!newton_column_parallel(sys)) return newton_layout(L, N, n, P).total;
+  // [J | -F] row-major as the evaluation writes it, then the solver's space
+  return align256(size_t(P) * 2 * L * N * (n + 1) * sizeof(double)) + ls_layout(L, N, n, P).total;
 }
 
 pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace, double* resid_out,
@@ -632,24 +655,54 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
   if (!x_inout || !workspace) return fail(PE_EINVAL, "x or workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
   const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  const bool big = newton_column_parallel(sys);
   const NewtonLayout lo = newton_layout(L, N, n, P);
   char* base = static_cast<char*>(workspace);
-  double* W = reinterpret_cast<double*>(base + lo.w_off);
+  double* W = reinterpret_cast<double*>(base);  // [J | -F], row stride n + 1
+  const int64_t w_pt = int64_t(2) * L * N * (n + 1);
   hipStream_t hs = static_cast<hipStream_t>(stream);
   OutView O;
   O.J = W;
   O.j_row = n + 1;
   O.j_plane = int64_t(N) * (n + 1);
-  O.j_pt = lo.w_pt;
+  O.j_pt = w_pt;
   O.F = W + n;
   O.f_row = n + 1;
   O.f_plane = O.j_plane;
-  O.f_pt = lo.w_pt;
+  O.f_pt = w_pt;
   O.f_sign = -1.0;
   hipError_t e = dispatch_rows(sys, P, x_inout, O, MODE_EVAL, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton eval launch: ") + hipGetErrorString(e));
-  e = dispatch_mgs(L, P, N, n, W, lo, base, x_inout, resid_out, hs);
+  if (big) {
+    void* ls = base + align256(size_t(P) * w_pt * sizeof(double));
+    e = dispatch_lstsq(L, ls_layout(L, N, n, P), ls, W, n + 1, O.j_plane, w_pt, x_inout, int64_t(2) * L * n, 1,
+                       resid_out, nullptr, nullptr, hs);
+  } else {
+    e = dispatch_mgs(L, P, N, n, W, lo, base, x_inout, resid_out, hs);
+  }
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton solve launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+size_t pe_lstsq_workspace_bytes(int32_t level, int32_t P, int32_t N, int32_t n) {
+  if ((level != 1 && level != 2 && level != 4) || P < 0 || N < 1 || n < 1) return 0;
+  return ls_layout(level, N, n, P).total;
+}
+
+pe_status pe_lstsq(int32_t level, int32_t P, int32_t N, int32_t n, const double* Ab, double* x, double* resid_out,
+                   double* R_out, double* Q_out, void* workspace, void* stream) {
+  if (level != 1 && level != 2 && level != 4) return fail(PE_EINVAL, "level must be 1, 2 or 4");
+  if (P < 0 || N < 1 || n < 1) return fail(PE_EINVAL, "need P >= 0, N >= 1, n >= 1");
+  if (N < n) return fail(PE_EUNSUPPORTED, "least squares needs N >= n");
+  if (N > kLsMaxRows) return fail(PE_EUNSUPPORTED, "the least-squares solve supports at most 4096 rows");
+  if (P > 65535) return fail(PE_EUNSUPPORTED, "at most 65535 points per call");
+  if (P == 0) return PE_OK;
+  if (!Ab || !x || !workspace) return fail(PE_EINVAL, "Ab, x or workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
+  const int64_t plane = int64_t(N) * (n + 1);
+  hipError_t e = dispatch_lstsq(level, ls_layout(level, N, n, P), workspace, Ab, n + 1, plane, 2 * level * plane, x,
+                                int64_t(2) * level * n, 0, resid_out, R_out, Q_out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("least-squares launch: ") + hipGetErrorString(e));
   return PE_OK;
 }
 
@@ -933,9 +986,16 @@ pe_status pe_batch_newton_step(const pe_batch* b, int32_t P, double* x_inout, vo
   if (P == 0) return PE_OK;
   if (!x_inout || !workspace) return fail(PE_EINVAL, "x or workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
+  // the batched step runs the one-workgroup solve for every system
   for (const pe_system* y : b->systems) {
     pe_status ps = newton_check(y, P);
     if (ps != PE_OK) return ps;
+    if (y->view.n + 1 > 1024) return fail(PE_EUNSUPPORTED, "the batched Gauss-Newton step supports n + 1 <= 1024");
+  }
+  {
+    const size_t lds = b->level == 1 ? mgs_lds_bytes<1>(b->maxN)
+                                     : (b->level == 2 ? mgs_lds_bytes<2>(b->maxN) : mgs_lds_bytes<4>(b->maxN));
+    if (lds > device_lds_limit()) return fail(PE_EUNSUPPORTED, "too many polynomials for the LDS pivot column");
   }
   const int L = b->level;
   char* base = static_cast<char*>(workspace);

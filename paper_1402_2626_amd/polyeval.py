@@ -47,6 +47,8 @@ SIGNATURES = {
     "pe_newton_step": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_batch_newton_workspace_bytes": (ctypes.c_size_t, [_p, _c_int]),
     "pe_batch_newton_step": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
+    "pe_lstsq_workspace_bytes": (ctypes.c_size_t, [_c_int, _c_int, _c_int, _c_int]),
+    "pe_lstsq": (_c_int, [_c_int, _c_int, _c_int, _c_int, _p, _p, _p, _p, _p, _p, _p]),
     "pe_autotune": (_c_int, [_p, _c_int, _p]),
     "pe_set_plan_cache": (_c_int, [ctypes.c_char_p]),
 }
@@ -251,6 +253,29 @@ class Batch:
         _check(_lib.pe_batch_newton_step(self._h, P, _ptr(x), _ptr(workspace), _ptr(resid), _stream(stream)),
                "pe_batch_newton_step")
         return x, resid
+
+
+def lstsq(Ab, want_R: bool = False, want_Q: bool = False, workspace=None, stream=None):
+    """Least-squares solution of A x = b for Ab[P, 2, L, N, n + 1] (float64
+    CUDA, column n = b) by modified Gram-Schmidt on [A b].  Returns
+    (x[P, 2, L, n], resid[P, 2], R[P, 2, L, n, n + 1] or None,
+    Q[P, 2, L, N, n] or None)."""
+    import torch
+    if Ab.dtype != torch.float64 or not Ab.is_cuda or not Ab.is_contiguous() or Ab.dim() != 5 or Ab.shape[1] != 2:
+        raise ValueError("Ab must be a contiguous float64 CUDA tensor [P, 2, L, N, n + 1]")
+    P, _, L, N, n1 = Ab.shape
+    n = n1 - 1
+    dev = Ab.device
+    x = torch.empty((P, 2, L, n), dtype=torch.float64, device=dev)
+    resid = torch.empty((P, 2), dtype=torch.float64, device=dev)
+    R = torch.empty((P, 2, L, n, n + 1), dtype=torch.float64, device=dev) if want_R else None
+    Q = torch.empty((P, 2, L, N, n), dtype=torch.float64, device=dev) if want_Q else None
+    if workspace is None:
+        nbytes = int(_lib.pe_lstsq_workspace_bytes(L, P, N, n))
+        workspace = torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=dev)
+    _check(_lib.pe_lstsq(L, P, N, n, _ptr(Ab), _ptr(x), _ptr(resid), _ptr(R), _ptr(Q), _ptr(workspace),
+                         _stream(stream)), "pe_lstsq")
+    return x, resid, R, Q
 
 
 def set_plan_cache(path: str | None):

@@ -101,6 +101,25 @@ def max_errors_entries(sys_, x, F, J, picks, parallel: bool = True):
     return max(r[0] for r in res), max(r[1] for r in res)
 
 
+def _value_ratio_job(args):
+    sub, x = args
+    X = O.point_from_limbs(x)
+    F = O.system_value_at(sub, X)
+    S = O.abs_sums_values(sub, x, range(sub.n_polys))
+    return max(O.cdy_abs_float(F[p]) / S[p] if S[p] else (0.0 if O.cdy_is_zero(F[p]) else float("inf"))
+               for p in range(sub.n_polys))
+
+
+def max_value_ratio(sys_, x, rows):
+    """max over rows p of |F_p(x)| / S_F(p), exactly from the limbs of x
+    ([2, L, n]): how far x is from a root, relative to the terms' size."""
+    rows = list(rows)
+    per = max(1, (len(rows) + 4 * workers() - 1) // (4 * workers()))
+    jobs = [(row_subsystem(sys_, rows[a:a + per]), x) for a in range(0, len(rows), per)]
+    with _pool(min(workers(), len(jobs))) as pool:
+        return max(pool.map(_value_ratio_job, jobs))
+
+
 def _pool(n):
     return mp.get_context("spawn").Pool(n)
 

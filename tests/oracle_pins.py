@@ -371,6 +371,37 @@ def pin_gauss_newton_linear() -> bool:
     return True
 
 
+def pin_lstsq_limbs() -> bool:
+    """The least-squares solve on its own: exactly representable
+    overdetermined, inconsistent complex data (with zeros on the diagonal)
+    against numpy.linalg.lstsq, and a consistent system whose solution is
+    known exactly."""
+    import oracle.exact as OE
+    rng = synth.rng_for(431)
+    for N, n in ((7, 4), (12, 12), (15, 6)):
+        C = rng.integers(-4, 5, size=(N, n)) + 1j * rng.integers(-4, 5, size=(N, n))
+        for i in range(min(N, n)):
+            C[i, i] = 0
+        b = rng.integers(-4, 5, size=N) + 1j * rng.integers(-4, 5, size=N)
+        Ab = np.zeros((2, 2, N, n + 1))
+        Ab[0, 0, :, :n], Ab[1, 0, :, :n] = C.real, C.imag
+        Ab[0, 0, :, n], Ab[1, 0, :, n] = b.real, b.imag
+        x = np.array([OE.cdy_to_complex(v) for v in OE.lstsq_limbs(Ab, prec=256)])
+        want = np.linalg.lstsq(C, b, rcond=None)[0]
+        if not np.max(np.abs(x - want)) < 1e-12 * max(1.0, np.max(np.abs(want))):
+            return False
+    # consistent: b = C x* with x* Gaussian integers, solution exact to 2^-380
+    C = rng.integers(-4, 5, size=(9, 5)) + 1j * rng.integers(-4, 5, size=(9, 5))
+    xs = rng.integers(-3, 4, size=5) + 1j * rng.integers(-3, 4, size=5)
+    b = C @ xs
+    Ab = np.zeros((2, 1, 9, 6))
+    Ab[0, 0, :, :5], Ab[1, 0, :, :5] = C.real, C.imag
+    Ab[0, 0, :, 5], Ab[1, 0, :, 5] = b.real, b.imag
+    x = OE.lstsq_limbs(Ab, prec=400)
+    return all(OE.cdy_abs_float(OE.cdy_add(x[j], OE.cdy_neg((int(xs[j].real), int(xs[j].imag), 0)))) < 2.0 ** -380
+               for j in range(5))
+
+
 def pin_gauss_newton_quadratic() -> bool:
     """Planted root of a square random system (constant -F_p(x*) rounded to
     quad double appended to each polynomial): from x* + 1e-3 noise the
@@ -497,5 +528,5 @@ ALL_PINS = [
     pin_quadratic_form, pin_finite_differences, pin_euler_homogeneity,
     pin_cyclic_at_one, pin_cyclic_at_roots_of_unity, pin_limb_rounding, pin_abs_sums,
     pin_gauss_newton_linear, pin_gauss_newton_quadratic, pin_columns_match_rows,
-    pin_abs_sums_positive, pin_error_metric_rejects,
+    pin_abs_sums_positive, pin_error_metric_rejects, pin_lstsq_limbs,
 ]

@@ -1,0 +1,258 @@
+"""The column-parallel least-squares solve (modified Gram-Schmidt on [A b],
+Sec. 3, Fig. 4, eq. (2); back substitution in stages, eq. (4)) and the
+Gauss-Newton steps that use it (Sec. 4), against the oracle and the
+invariants A = QR, Q^H Q = I."""
+import numpy as np
+import pytest
+
+import gpu_util as U
+import oracle as O
+from paper_1402_2626_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+UNIT = {1: 2.0 ** -53, 2: 2.0 ** -104, 4: 2.0 ** -206}
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1402_2626_amd import polyeval
+    return polyeval
+
+
+def _random_Ab(seed, L, P, N, n):
+    """[P, 2, L, N, n + 1] unit-circle entries at level L."""
+    rng = synth.rng_for(seed)
+    return np.stack([synth.unit_circle(rng, N * (n + 1), L).reshape(2, L, N, n + 1) for _ in range(P)])
+
+
+def _exact(a, *idx):
+    """Exact value of entry idx of a limb array a[2, L, ...]."""
+    return O.cdy_from_limbs(a[(0, slice(None)) + idx], a[(1, slice(None)) + idx])
+
+
+def _cond(Ab):
+    A = Ab[0, 0, :, :-1] + 1j * Ab[1, 0, :, :-1]
+    s = np.linalg.svd(A, compute_uv=False)
+    return s[0] / s[-1]
+
+
+def _check_factors(Ab, R, Q, L, pairs_qr, pairs_qq, kappa):
+    """A - QR and Q^H Q - I on sampled entries, exactly from the limbs:
+    |a_ij - sum_k q_ik r_kj| <= c u sum_k |q_ik| |r_kj| and
+    |sum_i conj(q_ik) q_il - delta_kl| <= c u kappa (MGS loses orthogonality
+    in proportion to the condition number)."""
+    N, n = Q.shape[2], Q.shape[3]
+    u = UNIT[L]
+    worst_qr = worst_qq = 0.0
+    for i, j in pairs_qr:
+        acc, mag = O.ZERO, 0.0
+        for k in range(j + 1):
+            q, r = _exact(Q, i, k), _exact(R, k, j)
+            acc = O.cdy_add(acc, O.cdy_mul(q, r))
+            mag += O.cdy_abs_float(q) * O.cdy_abs_float(r)
+        d = O.cdy_abs_float(O.cdy_add(_exact(Ab, i, j), O.cdy_neg(acc)))
+        worst_qr = max(worst_qr, d / (mag * u))
+    for k, l in pairs_qq:
+        acc = O.ZERO
+        for i in range(N):
+            acc = O.cdy_add(acc, O.cdy_mul(O.cdy_conj(_exact(Q, i, k)), _exact(Q, i, l)))
+        if k == l:
+            acc = O.cdy_add(acc, (-1, 0, 0))
+        worst_qq = max(worst_qq, O.cdy_abs_float(acc) / (u * kappa))
+    # R: upper triangular with a real positive diagonal
+    for j in range(n):
+        assert np.all(R[:, :, j + 1:, j] == 0.0)
+        assert R[0, 0, j, j] > 0.0 and np.all(R[1, :, j, j] == 0.0)
+    return worst_qr, worst_qq
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_lstsq_matches_oracle(pe, L):
+    """Overdetermined, inconsistent unit-circle problems (N = 40, n = 29, two
+    points): x against the oracle's Householder solve at 400 bits within
+    c N kappa u_L |x|; the factors satisfy A = QR and Q^H Q = I to the level's
+    precision; y (column n of R) equals Q^H b."""
+    import torch
+    N, n, P = 40, 29, 2
+    Ab = _random_Ab((801, L), L, P, N, n)
+    x, resid, R, Q = pe.lstsq(U.to_device(Ab), want_R=True, want_Q=True)
+    torch.cuda.synchronize()
+    x, resid, R, Q = x.cpu().numpy(), resid.cpu().numpy(), R.cpu().numpy(), Q.cpu().numpy()
+    u = UNIT[L]
+    for pt in range(P):
+        kappa = _cond(Ab[pt])
+        xs = O.lstsq_limbs(Ab[pt], prec=400)
+        xn = max(O.cdy_abs_float(v) for v in xs)
+        err = max(O.cdy_abs_float(O.cdy_add(_exact(x[pt], j), O.cdy_neg(xs[j]))) for j in range(n))
+        U.flush(f"lstsq L={L} pt={pt}: |x - x*| / |x*| = {err / xn:.2e}, kappa = {kappa:.1f}")
+        assert err <= 10 * N * kappa * u * xn, (pt, err, xn, kappa)
+        assert resid[pt, 1] > 0.0
+        b = Ab[pt, :, :, :, n]
+        assert abs(resid[pt, 0] - np.linalg.norm(b[0, 0] + 1j * b[1, 0])) <= 1e-12 * resid[pt, 0]
+        pairs = [(i, j) for i in (0, 7, N - 1) for j in (0, 13, n - 1, n)]
+        wqr, wqq = _check_factors(Ab[pt], R[pt], Q[pt], L, pairs, [(0, 0), (0, 5), (11, 28), (28, 28)], kappa)
+        assert wqr <= 64 * N and wqq <= 64 * N, (wqr, wqq)
+
+
+def test_lstsq_large_double_double(pe):
+    """N = 1100 rows, n = 1000 unknowns in double double (the 256 x 8 sweep):
+    sampled entries of A - QR and Q^H Q - I exactly, and x against numpy's
+    least squares on the leading limbs (float64 accuracy)."""
+    import torch
+    L, N, n = 2, 1100, 1000
+    Ab = _random_Ab(811, L, 1, N, n)
+    U.flush("lstsq 1100 x 1000 DD: solving")
+    x, resid, R, Q = pe.lstsq(U.to_device(Ab), want_R=True, want_Q=True)
+    torch.cuda.synchronize()
+    x, R, Q = x.cpu().numpy()[0], R.cpu().numpy()[0], Q.cpu().numpy()[0]
+    kappa = _cond(Ab[0])
+    A = Ab[0, 0, :, :n] + 1j * Ab[0, 1, :, :n]
+    b = Ab[0, 0, :, n] + 1j * Ab[0, 1, :, n]
+    want = np.linalg.lstsq(A, b, rcond=None)[0]
+    got = x[0, 0] + 1j * x[1, 0]
+    rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    U.flush(f"lstsq 1100 x 1000 DD: kappa = {kappa:.0f}, |x - x_numpy| / |x| = {rel:.2e}")
+    assert rel <= 1e3 * kappa * 2.0 ** -53
+    rng = synth.rng_for(812)
+    pairs_qr = [(int(rng.integers(N)), int(rng.integers(n + 1))) for _ in range(24)] + [(N - 1, n), (0, 0)]
+    pairs_qq = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(16)] + [(n - 1, n - 1), (0, n - 1)]
+    wqr, wqq = _check_factors(Ab[0], R, Q, L, pairs_qr, pairs_qq, kappa)
+    U.flush(f"lstsq 1100 x 1000 DD: A - QR {wqr:.1f} u, Q^H Q - I {wqq:.2e} u kappa")
+    assert wqr <= 64 * N and wqq <= 64 * N, (wqr, wqq)
+
+
+@pytest.mark.parametrize("N, n", [(2048, 160), (3000, 24)])
+def test_lstsq_quad_double_tall(pe, N, n):
+    """Quad double with the 256 x 8 and 256 x 16 sweeps (columns of 2048 and
+    3000 rows): sampled A - QR and Q^H Q - I exactly; for the narrow problem
+    also x against the oracle's Householder solve."""
+    import torch
+    L = 4
+    Ab = _random_Ab((821, N), L, 1, N, n)
+    x, resid, R, Q = pe.lstsq(U.to_device(Ab), want_R=True, want_Q=True)
+    torch.cuda.synchronize()
+    x, R, Q = x.cpu().numpy()[0], R.cpu().numpy()[0], Q.cpu().numpy()[0]
+    kappa = _cond(Ab[0])
+    rng = synth.rng_for((822, N))
+    pairs_qr = [(int(rng.integers(N)), int(rng.integers(n + 1))) for _ in range(12)] + [(N - 1, n)]
+    pairs_qq = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(6)] + [(n - 1, n - 1)]
+    wqr, wqq = _check_factors(Ab[0], R, Q, L, pairs_qr, pairs_qq, kappa)
+    assert wqr <= 64 * N and wqq <= 64 * N, (wqr, wqq)
+    if n <= 32:
+        xs = O.lstsq_limbs(Ab[0], prec=500)
+        xn = max(O.cdy_abs_float(v) for v in xs)
+        err = max(O.cdy_abs_float(O.cdy_add(_exact(x, j), O.cdy_neg(xs[j]))) for j in range(n))
+        assert err <= 10 * N * kappa * UNIT[L] * xn, (err, xn, kappa)
+
+
+def test_lstsq_singular(pe):
+    """Two equal columns: the second pivot is numerically zero; x = 0 and the
+    residual slot reports -1; the other point (full rank) is solved."""
+    import torch
+    L, N, n = 2, 300, 200
+    Ab = _random_Ab(831, L, 2, N, n)
+    Ab[0, :, :, :, 7] = Ab[0, :, :, :, 3]
+    x, resid, _, _ = pe.lstsq(U.to_device(Ab))
+    torch.cuda.synchronize()
+    x, resid = x.cpu().numpy(), resid.cpu().numpy()
+    assert resid[0, 1] == -1.0 and np.all(x[0] == 0.0)
+    assert resid[1, 1] > 0.0 and np.isfinite(x[1]).all()
+
+
+def _newton_backward_error(sys_, x0, x1, rows):
+    """For sampled rows p, |F_p(x0) + sum_j J_pj(x0) dx_j| / (|F_p| + sum_j
+    |J_pj| |dx_j|) with dx = x1 - x0, all exact from the limbs: the backward
+    error of the step's linear solve."""
+    X0 = O.point_from_limbs(x0)
+    X1 = O.point_from_limbs(x1)
+    dX = [O.cdy_add(X1[j], O.cdy_neg(X0[j])) for j in range(len(X0))]
+    Fx, Jx = O.eval_rows(sys_, x0, rows)
+    worst = 0.0
+    for p in rows:
+        acc, mag = Fx[p], O.cdy_abs_float(Fx[p])
+        for j, v in Jx[p].items():
+            acc = O.cdy_add(acc, O.cdy_mul(v, dX[j]))
+            mag += O.cdy_abs_float(v) * O.cdy_abs_float(dX[j])
+        worst = max(worst, O.cdy_abs_float(acc) / mag)
+    return worst
+
+
+@pytest.mark.parametrize("L, n", [(2, 1024), (4, 512)])
+def test_newton_chandrasekhar_large(pe, L, n):
+    """Chandrasekhar's H-equation (Sec. 5.2, c = 33/64) at n = 1024 in double
+    double and n = 512 in quad double from H = 1, through the column-parallel
+    solve: the first step's linear solve has a backward error of a few u_L
+    on sampled rows (exact J and F at H = 1 from the oracle); the iterates
+    converge quadratically to the level's floor; at the last iterate F is
+    zero to the tolerance on every row (oracle)."""
+    import torch
+    sys_ = synth.chandrasekhar_system(n, L)
+    x0 = np.zeros((2, L, n))
+    x0[0, 0, :] = 1.0
+    S = pe.System.from_sparse(sys_)
+    xd = U.to_device(x0[None])
+    ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+    iterates, res = [x0], []
+    for it in range(7 if L == 2 else 9):
+        _, r = S.newton_step(xd, workspace=ws)
+        torch.cuda.synchronize()
+        iterates.append(xd.cpu().numpy()[0].copy())
+        res.append(r.cpu().numpy()[0].copy())
+        U.flush(f"chandrasekhar n={n} L={L}: step {it}: |F| = {res[-1][0]:.3e}, |dx| = {res[-1][1]:.3e}")
+    S.close()
+    u = UNIT[L]
+    be = _newton_backward_error(sys_, iterates[0], iterates[1], [0, 1, n // 2, n - 2, n - 1])
+    assert be <= 64 * n * u, be
+    last = O.point_from_limbs(iterates[-1])
+    errs = [max(O.cdy_abs_float(O.cdy_add(O.cdy_from_limbs(x[0, :, j], x[1, :, j]), O.cdy_neg(last[j])))
+                for j in range(n)) for x in iterates[:-1]]
+    for a, b in zip(errs, errs[1:]):
+        assert b <= 1e4 * a * a + 1e5 * u, errs
+    assert errs[-1] <= 1e5 * u, errs
+    assert all(r[1] >= 0.0 for r in res)
+    eF = U.max_value_ratio(sys_, iterates[-1], range(n))
+    assert eF <= U.tolerance(sys_) * 8, eF
+    xg = iterates[-1]
+    assert np.all(xg[0, 0] > 1.0) and np.all(np.abs(xg[1, 0]) <= 1e4 * u)
+
+
+def test_newton_large_graph_replay(pe):
+    """A Newton step through the column-parallel solve (n = 200, about 200
+    launches) captured in a HIP graph and replayed three times with eager work
+    in between equals the eager steps bit for bit."""
+    import torch
+    sys_ = synth.random_system(841, 2, n_vars=200, n_polys=230, m=8, k=3, exp_lo=1, exp_hi=2)
+    xs = synth.unit_circle_points(synth.rng_for(842), 1, 200, 2)[0]
+    planted = O.plant_root(sys_, xs)
+    S = pe.System.from_sparse(planted)
+    x0 = synth.perturbed_start(843, xs, 1e-5)[None]
+    ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+    resid = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+    xe = U.to_device(x0)
+    eager = []
+    for _ in range(3):
+        S.newton_step(xe, workspace=ws, resid=resid)
+        torch.cuda.synchronize()
+        eager.append(xe.cpu().numpy().copy())
+    s = torch.cuda.Stream()
+    xg = U.to_device(x0)
+    S.newton_step(xg.clone(), workspace=ws, resid=resid, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        S.newton_step(xg, workspace=ws, resid=resid, stream=s)
+    xg.copy_(U.to_device(x0))
+    torch.cuda.synchronize()
+    for it in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (torch.randn(4096, device="cuda") * 2).sum().item()
+        assert np.array_equal(xg.cpu().numpy(), eager[it]), it
+    d = max(O.cdy_abs_float(O.cdy_add(O.cdy_from_limbs(eager[-1][0, 0, :, j], eager[-1][0, 1, :, j]),
+                                        O.cdy_neg(O.cdy_from_limbs(xs[0, :, j], xs[1, :, j])))) for j in range(200))
+    assert d <= 1e-26, d
+    S.close()

@@ -253,6 +253,29 @@ def _mut_rel_error_lenient(got_re, got_im, exact, S):
     return E.cdy_abs_float(d) / (1e6 * S)
 
 
+def _mut_lstsq_transpose(A, b):
+    import mpmath
+    Q, Rm = mpmath.qr(A, mode="skinny")
+    return mpmath.lu_solve(Rm, Q.T * b)  # Q^T instead of Q^H
+
+
+def _mut_abs_values_no_power(sys_, x, rows):
+    import numpy as _np
+    ax = _np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+    ac = _np.hypot(sys_.coef[0].sum(axis=0), sys_.coef[1].sum(axis=0))
+    SF = {}
+    for p in rows:
+        sf = 0.0
+        for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+            vs, ds = sys_.monomial(t)
+            m = float(ac[t])
+            for v in vs:
+                m *= float(ax[v])  # exponents dropped
+            sf += m
+        SF[p] = sf
+    return SF
+
+
 MUTANTS = {
     "power_off_by_one": ("_power", _mut_power_off_by_one),
     "mul_sign": ("cdy_mul", _mut_mul_sign),
@@ -272,6 +295,8 @@ MUTANTS = {
     "abs_rows_no_power": ("abs_sums_rows", _make_abs_sums_rows_no_power()),
     "metric_zero_scale_accepts": ("rel_error", _mut_rel_error_zero_scale_ok),
     "metric_lenient": ("rel_error", _mut_rel_error_lenient),
+    "lstsq_transpose_not_adjoint": ("_lstsq_householder", _mut_lstsq_transpose),
+    "abs_values_no_power": ("abs_sums_values", _mut_abs_values_no_power),
 }
 
 
