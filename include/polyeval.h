@@ -210,6 +210,28 @@ size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P);
 pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace,
                          double* resid_out, void* stream);
 
+/* ------------------------------------------------------------------ Newton homotopy
+ * The Newton homotopy h(x, t) = f(x) - t c with c = f(z) (Sec. 5.3): at
+ * t = 1 the point z is a solution; following the solution path as t goes
+ * from 1 to 0 leads to a solution of f(x) = 0.  c is device [P][2][L][N],
+ * one vector per point (path); x, workspace and resid_out as in
+ * pe_newton_step (the same workspace size; resid_out[p][0] is the norm of
+ * the step's right-hand side).  Kernels only: capturable in a HIP graph.
+ *
+ * pe_homotopy_newton_step: one Gauss-Newton step on h(., t) at fixed t
+ *   (A = J(x), b = -(f(x) - t c)).
+ * pe_homotopy_predict: the Euler predictor from t to t + dt along the path,
+ *   x += dx with J(x) dx = c dt (least squares).
+ * pe_homotopy_track: t from 1 to 0 in `steps` equal steps; per step one
+ *   predictor and `corrector_iters` Newton steps at the new t (t_k = 1 - k /
+ *   steps, computed in double). */
+pe_status pe_homotopy_newton_step(const pe_system* sys, int32_t P, double* x_inout, const double* c, double t,
+                                  void* workspace, double* resid_out, void* stream);
+pe_status pe_homotopy_predict(const pe_system* sys, int32_t P, double* x_inout, const double* c, double dt,
+                              void* workspace, double* resid_out, void* stream);
+pe_status pe_homotopy_track(const pe_system* sys, int32_t P, double* x_inout, const double* c, int32_t steps,
+                            int32_t corrector_iters, void* workspace, double* resid_out, void* stream);
+
 /* The same for every system of a batch, x in the packed batch layout;
  * resid_out is [S][P][2].  Every system is solved by one workgroup per point:
  * n + 1 <= 1024 and the largest pivot column within one workgroup's LDS. */

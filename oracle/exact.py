@@ -42,7 +42,7 @@ __all__ = [
     "eval_rows", "eval_columns", "eval_system", "abs_sums_rows", "rel_error",
     "max_rel_error_rows", "adjoint_exact", "adjoint_columns", "gauss_newton_step_mp",
     "system_value_at", "round_point", "speelpenning_straightforward", "plant_root",
-    "abs_sums_columns", "abs_sums_values", "lstsq_limbs",
+    "abs_sums_columns", "abs_sums_values", "lstsq_limbs", "homotopy_step_mp", "homotopy_track_mp",
 ]
 
 # --------------------------------------------------------------------------
@@ -434,6 +434,61 @@ def gauss_newton_step_mp(sys_, X_exact, prec: int = 512):
         dinf = float(max(abs(dx[j]) for j in range(n))) if n else 0.0
         newX = [_mpc_to_cdy(mpc(X_exact[j]) + dx[j]) for j in range(n)]
     return newX, (fnorm, dinf)
+
+
+def _exact_F_J(sys_, X_exact):
+    """Exact F and rows of J at the exact point X_exact."""
+    F, J = {}, {}
+    for p in range(sys_.n_polys):
+        f = ZERO
+        jrow = {}
+        for t in range(int(sys_.poly_ptr[p]), int(sys_.poly_ptr[p + 1])):
+            vs, ds = sys_.monomial(t)
+            value, partials = monomial_value_and_partials(_coef(sys_, t), [X_exact[v] for v in vs], ds)
+            f = cdy_add(f, value)
+            for r, v in enumerate(vs):
+                v = int(v)
+                jrow[v] = cdy_add(jrow[v], partials[r]) if v in jrow else partials[r]
+        F[p], J[p] = f, jrow
+    return F, J
+
+
+def homotopy_step_mp(sys_, X_exact, c_exact, wF: float, wc: float, prec: int = 512):
+    """One step x += dx of the Newton homotopy f(x) - t c (Sec. 5.3): dx
+    solves J(x) dx = wF (-f(x)) + wc c in the least-squares sense (Householder
+    QR at ``prec`` bits); wF = 1, wc = t is Newton's method on f(x) - t c = 0
+    at fixed t, wF = 0, wc = dt the Euler step along the path.  wF and wc are
+    doubles, taken exactly.  Returns the new exact point."""
+    import mpmath
+    n, N = sys_.n_vars, sys_.n_polys
+    F, J = _exact_F_J(sys_, X_exact)
+    with mpmath.workprec(prec):
+        def mpc(a):
+            return mpmath.mpc(mpmath.ldexp(a[0], a[2]), mpmath.ldexp(a[1], a[2]))
+        A = mpmath.matrix(N, n)
+        b = mpmath.matrix(N, 1)
+        mwF, mwc = mpmath.mpf(wF), mpmath.mpf(wc)
+        for p in range(N):
+            for j, val in J[p].items():
+                A[p, j] = mpc(val)
+            b[p] = -mwF * mpc(F[p]) + mwc * mpc(c_exact[p])
+        dx = _lstsq_householder(A, b)
+        return [_mpc_to_cdy(mpc(X_exact[j]) + dx[j]) for j in range(n)]
+
+
+def homotopy_track_mp(sys_, Z_exact, c_exact, steps: int, corrector_iters: int, prec: int = 512):
+    """Follow f(x) - t c = 0 from t = 1 (x = z) to t = 0 in ``steps`` equal
+    steps of t (t_k = 1 - k / steps rounded to double, as a caller computes
+    it), each an Euler predictor and ``corrector_iters`` Newton steps at the
+    new t.  Returns the exact end point."""
+    X = list(Z_exact)
+    for k in range(1, steps + 1):
+        t0 = 1.0 - (k - 1) / steps
+        t1 = 0.0 if k == steps else 1.0 - k / steps
+        X = homotopy_step_mp(sys_, X, c_exact, 0.0, t1 - t0, prec)
+        for _ in range(corrector_iters):
+            X = homotopy_step_mp(sys_, X, c_exact, 1.0, t1, prec)
+    return X
 
 
 def _lstsq_householder(A, b):

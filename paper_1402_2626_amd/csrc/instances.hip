@@ -23,6 +23,8 @@ template hipError_t launch_mgs<PE_LEVEL>(int, int, int, double*, int64_t, double
                                          double*, hipStream_t);
 template hipError_t launch_mgs_batch<PE_LEVEL>(int, int, int, const BatchNewtonDesc*, const int*, double*, double*,
                                                double*, double*, double*, hipStream_t);
+template hipError_t launch_rhs_shift<PE_LEVEL>(double*, int64_t, int64_t, int64_t, int, int, int, const double*, double,
+                                               double, hipStream_t);
 #elif PE_KIND == 4
 template hipError_t launch_lstsq<PE_LEVEL>(const LsLayout&, void*, const double*, int64_t, int64_t, int64_t, double*,
                                            int64_t, int, double*, double*, double*, hipStream_t);

@@ -72,6 +72,10 @@ template <int L>
 hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc, const int* order, double* W,
                             double* R, double* Y, double* x, double* resid, hipStream_t st);
 
+template <int L>
+hipError_t launch_rhs_shift(double* W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P, const double* c,
+                            double wF, double wc, hipStream_t st);
+
 // Column-parallel least-squares solve of the augmented matrices [A b] given
 // row-major at A (row stride ld, component plane stride a_plane, point stride
 // a_pt; see lstsq_kernels.hpp), writing x (x_pt per point; add = 1 adds the
@@ -251,6 +255,15 @@ hipError_t launch_mgs_batch(int S, int P, int maxN, const BatchNewtonDesc* desc,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(S) * P)), dim3(kMgsThreads), lds, st, desc, order, P, W, R, Y, x,
                      resid);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_rhs_shift(double* W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P, const double* c,
+                            double wF, double wc, hipStream_t st) {
+  const int64_t tot = int64_t(P) * N;
+  hipLaunchKernelGGL(rhs_shift_kernel<L>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, W, w_pt, plane, ld, N, n,
+                     P, c, wF, wc);
   return hipGetLastError();
 }
 

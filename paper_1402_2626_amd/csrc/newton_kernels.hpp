@@ -198,6 +198,23 @@ __global__ __launch_bounds__(T) void mgs_solve_batch_kernel(const BatchNewtonDes
                         resid ? resid + (int64_t(s) * P + pt) * 2 : nullptr, lds);
 }
 
+// Right-hand side of a Newton step on the homotopy h(x, t) = f(x) - t c
+// (Sec. 5.3: c = f(z), so z solves h at t = 1).  The evaluation has written
+// b = -f(x) into column n of the augmented matrices (row-major planar, point
+// stride w_pt, plane stride plane, row stride ld); this replaces it by
+// wF b + wc c_p with wF in {0, 1}: (1, t) is the corrector at t, (0, dt) the
+// Euler predictor J dx = c dt.  c is [P][2L][N]; grid over P * N.
+template <int L>
+__global__ void rhs_shift_kernel(double* __restrict__ W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P,
+                                 const double* __restrict__ c, double wF, double wc) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(P) * N) return;
+  const int p = int(idx / N), i = int(idx - int64_t(p) * N);
+  double* b = W + p * w_pt + int64_t(i) * ld + n;
+  const C<L> sc = c_mul_d(load_planar<L>(c + int64_t(p) * 2 * L * N, N, i), wc);
+  store_planar(b, plane, 0, wF == 0.0 ? sc : c_add(load_planar<L>(b, plane, 0), sc));
+}
+
 template <int L>
 __host__ __device__ inline size_t mgs_lds_bytes(int N) {
   return size_t(N) * 2 * L * sizeof(double) + 2 * L * sizeof(double) + kMgsThreads * sizeof(double) + 16;

@@ -646,8 +646,24 @@ size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P) {
   return align256(size_t(P) * 2 * L * N * (n + 1) * sizeof(double)) + ls_layout(L, N, n, P).total;
 }
 
-pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace, double* resid_out,
-                         void* stream) {
+}  // extern "C"
+
+namespace {
+
+hipError_t dispatch_rhs_shift(int L, double* W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P,
+                              const double* c, double wF, double wc, hipStream_t st) {
+  switch (L) {
+    case 1: return launch_rhs_shift<1>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
+    case 2: return launch_rhs_shift<2>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
+    case 4: return launch_rhs_shift<4>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// One step x += dx with J(x) dx = b in the least-squares sense, where
+// b = -f(x) (c null), or b = wF (-f(x)) + wc c (the homotopy f(x) - t c).
+pe_status newton_step_impl(const pe_system* sys, int32_t P, double* x_inout, const double* c, double wF, double wc,
+                           void* workspace, double* resid_out, void* stream) {
   if (!sys) return fail(PE_EINVAL, "system is NULL");
   pe_status ps = newton_check(sys, P);
   if (ps != PE_OK) return ps;
@@ -673,6 +689,10 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
   O.f_sign = -1.0;
   hipError_t e = dispatch_rows(sys, P, x_inout, O, MODE_EVAL, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton eval launch: ") + hipGetErrorString(e));
+  if (c) {
+    e = dispatch_rhs_shift(L, W, w_pt, O.j_plane, n + 1, N, n, P, c, wF, wc, hs);
+    if (e != hipSuccess) return fail(PE_EDEVICE, std::string("homotopy right-hand side: ") + hipGetErrorString(e));
+  }
   if (big) {
     void* ls = base + align256(size_t(P) * w_pt * sizeof(double));
     e = dispatch_lstsq(L, ls_layout(L, N, n, P), ls, W, n + 1, O.j_plane, w_pt, x_inout, int64_t(2) * L * n, 1,
@@ -681,6 +701,44 @@ pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void*
     e = dispatch_mgs(L, P, N, n, W, lo, base, x_inout, resid_out, hs);
   }
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton solve launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pe_status pe_newton_step(const pe_system* sys, int32_t P, double* x_inout, void* workspace, double* resid_out,
+                         void* stream) {
+  return newton_step_impl(sys, P, x_inout, nullptr, 1.0, 0.0, workspace, resid_out, stream);
+}
+
+pe_status pe_homotopy_newton_step(const pe_system* sys, int32_t P, double* x_inout, const double* c, double t,
+                                  void* workspace, double* resid_out, void* stream) {
+  if (!c) return fail(PE_EINVAL, "c is NULL");
+  if (!std::isfinite(t)) return fail(PE_EINVAL, "t must be finite");
+  return newton_step_impl(sys, P, x_inout, c, 1.0, t, workspace, resid_out, stream);
+}
+
+pe_status pe_homotopy_predict(const pe_system* sys, int32_t P, double* x_inout, const double* c, double dt,
+                              void* workspace, double* resid_out, void* stream) {
+  if (!c) return fail(PE_EINVAL, "c is NULL");
+  if (!std::isfinite(dt)) return fail(PE_EINVAL, "dt must be finite");
+  return newton_step_impl(sys, P, x_inout, c, 0.0, dt, workspace, resid_out, stream);
+}
+
+pe_status pe_homotopy_track(const pe_system* sys, int32_t P, double* x_inout, const double* c, int32_t steps,
+                            int32_t corrector_iters, void* workspace, double* resid_out, void* stream) {
+  if (steps < 1 || corrector_iters < 0) return fail(PE_EINVAL, "need steps >= 1 and corrector_iters >= 0");
+  if (!c) return fail(PE_EINVAL, "c is NULL");
+  for (int k = 1; k <= steps; ++k) {
+    // t from 1 down to 0 in equal steps; t_k computed, not accumulated
+    const double t0 = 1.0 - double(k - 1) / double(steps), t1 = k == steps ? 0.0 : 1.0 - double(k) / double(steps);
+    pe_status st = newton_step_impl(sys, P, x_inout, c, 0.0, t1 - t0, workspace, resid_out, stream);
+    for (int it = 0; it < corrector_iters && st == PE_OK; ++it)
+      st = newton_step_impl(sys, P, x_inout, c, 1.0, t1, workspace, resid_out, stream);
+    if (st != PE_OK) return st;
+  }
   return PE_OK;
 }
 

@@ -47,6 +47,9 @@ SIGNATURES = {
     "pe_newton_step": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_batch_newton_workspace_bytes": (ctypes.c_size_t, [_p, _c_int]),
     "pe_batch_newton_step": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
+    "pe_homotopy_newton_step": (_c_int, [_p, _c_int, _p, _p, ctypes.c_double, _p, _p, _p]),
+    "pe_homotopy_predict": (_c_int, [_p, _c_int, _p, _p, ctypes.c_double, _p, _p, _p]),
+    "pe_homotopy_track": (_c_int, [_p, _c_int, _p, _p, _c_int, _c_int, _p, _p, _p]),
     "pe_lstsq_workspace_bytes": (ctypes.c_size_t, [_c_int, _c_int, _c_int, _c_int]),
     "pe_lstsq": (_c_int, [_c_int, _c_int, _c_int, _c_int, _p, _p, _p, _p, _p, _p, _p]),
     "pe_autotune": (_c_int, [_p, _c_int, _p]),
@@ -188,6 +191,42 @@ class System:
             resid = torch.empty((P, 2), dtype=torch.float64, device=x.device)
         _check(_lib.pe_newton_step(self._h, P, _ptr(x), _ptr(workspace), _ptr(resid), _stream(stream)),
                "pe_newton_step")
+        return x, resid
+
+    def _homotopy_args(self, x, c, workspace, resid):
+        import torch
+        self._check_x(x)
+        P = x.shape[0]
+        if c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous() or \
+                tuple(c.shape) != (P, 2, self.level, self.n_polys):
+            raise ValueError("c must be a contiguous float64 CUDA tensor [P, 2, L, N]")
+        if workspace is None:
+            nbytes = self.newton_workspace_bytes(P)
+            workspace = torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=x.device)
+        if resid is None:
+            resid = torch.empty((P, 2), dtype=torch.float64, device=x.device)
+        return P, workspace, resid
+
+    def homotopy_newton_step(self, x, c, t: float, workspace=None, resid=None, stream=None):
+        """One Gauss-Newton step on f(x) - t c = 0, in place on x[P, 2, L, n]."""
+        P, workspace, resid = self._homotopy_args(x, c, workspace, resid)
+        _check(_lib.pe_homotopy_newton_step(self._h, P, _ptr(x), _ptr(c), float(t), _ptr(workspace), _ptr(resid),
+                                            _stream(stream)), "pe_homotopy_newton_step")
+        return x, resid
+
+    def homotopy_predict(self, x, c, dt: float, workspace=None, resid=None, stream=None):
+        """Euler predictor x += dx, J(x) dx = c dt, in place."""
+        P, workspace, resid = self._homotopy_args(x, c, workspace, resid)
+        _check(_lib.pe_homotopy_predict(self._h, P, _ptr(x), _ptr(c), float(dt), _ptr(workspace), _ptr(resid),
+                                        _stream(stream)), "pe_homotopy_predict")
+        return x, resid
+
+    def homotopy_track(self, x, c, steps: int, corrector_iters: int = 3, workspace=None, resid=None, stream=None):
+        """Track f(x) - t c = 0 from t = 1 (x = z with c = f(z)) to t = 0, in
+        place on x[P, 2, L, n]."""
+        P, workspace, resid = self._homotopy_args(x, c, workspace, resid)
+        _check(_lib.pe_homotopy_track(self._h, P, _ptr(x), _ptr(c), int(steps), int(corrector_iters),
+                                      _ptr(workspace), _ptr(resid), _stream(stream)), "pe_homotopy_track")
         return x, resid
 
     def autotune(self, P: int = 1, stream=None):

@@ -120,6 +120,43 @@ def max_value_ratio(sys_, x, rows):
         return max(pool.map(_value_ratio_job, jobs))
 
 
+def _values_job(args):
+    sub, x = args
+    return O.system_value_at(sub, O.point_from_limbs(x))
+
+
+def values_at(sys_, x):
+    """[2, L, N] limbs of F(x) computed exactly by the oracle (rows in
+    parallel) and rounded to the system's level."""
+    rows = list(range(sys_.n_polys))
+    per = max(1, (len(rows) + 4 * workers() - 1) // (4 * workers()))
+    jobs = [(row_subsystem(sys_, rows[a:a + per]), x) for a in range(0, len(rows), per)]
+    with _pool(min(workers(), len(jobs))) as pool:
+        vals = [v for part in pool.map(_values_job, jobs) for v in part]
+    return O.round_point(vals, sys_.level)
+
+
+def _shift_job(args):
+    sub, x, c, t = args
+    X = O.point_from_limbs(x)
+    F = O.system_value_at(sub, X)
+    S = O.abs_sums_values(sub, x, range(sub.n_polys))
+    C = O.point_from_limbs(c)
+    m, e = O.dy_from_float(t)
+    worst = 0.0
+    for p in range(sub.n_polys):
+        tc = (C[p][0] * m, C[p][1] * m, C[p][2] + e)
+        worst = max(worst, O.cdy_abs_float(O.cdy_add(F[p], O.cdy_neg(tc))) / (S[p] + O.cdy_abs_float(tc)))
+    return worst
+
+
+def max_shift_ratio(sys_, x, c, t):
+    """max over rows of |f_p(x) - t c_p| / (S_F(p) + |t c_p|), exactly."""
+    jobs = [(row_subsystem(sys_, [p]), x, c[:, :, p:p + 1], t) for p in range(sys_.n_polys)]
+    with _pool(min(workers(), len(jobs))) as pool:
+        return max(pool.map(_shift_job, jobs))
+
+
 def _pool(n):
     return mp.get_context("spawn").Pool(n)
 

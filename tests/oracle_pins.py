@@ -402,6 +402,54 @@ def pin_lstsq_limbs() -> bool:
                for j in range(5))
 
 
+def pin_homotopy_square_root() -> bool:
+    """f(x) = x^2 - 4 from z = 3 (c = f(z) = 5): the path of x^2 - 4 - 5t = 0
+    is x(t) = sqrt(4 + 5t), so tracking to t = 0 ends at the root 2; a single
+    corrector at t = 1/2 from x(1/2) + 1e-3 lands on sqrt(6.5) quadratically."""
+    import mpmath
+    import oracle.exact as OE
+    sys_ = synth.from_monomial_lists(2, 1, [[(1.0, [(0, 2)]), (-4.0, [])]])
+    end = OE.homotopy_track_mp(sys_, [(3, 0, 0)], [(5, 0, 0)], steps=8, corrector_iters=6, prec=400)
+    if OE.cdy_abs_float(OE.cdy_add(end[0], (-2, 0, 0))) > 1e-100:
+        return False
+    with mpmath.workprec(400):
+        xh = mpmath.sqrt(mpmath.mpf(6.5))
+        start = OE._mpc_to_cdy(mpmath.mpc(xh + mpmath.mpf(2) ** -10))
+        X = OE.homotopy_step_mp(sys_, [start], [(5, 0, 0)], 1.0, 0.5, prec=400)
+        err = abs(mpmath.ldexp(X[0][0], X[0][2]) - xh)
+        return 1e-9 < err < 1e-5  # one Newton step: (2^-10)^2 / (2 x) ~ 2e-7
+
+
+def pin_homotopy_decoupled_squares() -> bool:
+    """Decoupled squares x_j^2 - a_j (complex a_j, random start z): each
+    path is x_j(t)^2 = a_j + t (z_j^2 - a_j), whose continuous branch from z_j
+    is followed here by 4000 small steps of mpmath's square root with the
+    sign kept continuous; the tracker's end point matches it."""
+    import mpmath
+    import oracle.exact as OE
+    rng = synth.rng_for(441)
+    n = 3
+    a = rng.integers(-4, 5, size=n) + 1j * rng.integers(1, 5, size=n)
+    z = rng.integers(-3, 4, size=n) + 1j * rng.integers(-3, 4, size=n) + 0.5
+    polys = [[(1.0, [(j, 2)]), (-a[j], [])] for j in range(n)]
+    sys_ = synth.from_monomial_lists(2, n, polys)
+    Z = [OE._mpc_to_cdy(mpmath.mpc(complex(v))) for v in z]
+    c = [OE.cdy_add(OE.cdy_mul(Zj, Zj), OE._mpc_to_cdy(mpmath.mpc(-complex(a[j])))) for j, Zj in enumerate(Z)]
+    end = OE.homotopy_track_mp(sys_, Z, c, steps=16, corrector_iters=6, prec=300)
+    with mpmath.workprec(200):
+        for j in range(n):
+            x = mpmath.mpc(complex(z[j]))
+            w0 = mpmath.mpc(complex(a[j]))
+            w1 = mpmath.mpc(complex(z[j])) ** 2 - w0
+            for k in range(1, 4001):
+                r = mpmath.sqrt(w0 + (1 - mpmath.mpf(k) / 4000) * w1)
+                x = r if abs(r - x) < abs(r + x) else -r
+            got = mpmath.mpc(mpmath.ldexp(end[j][0], end[j][2]), mpmath.ldexp(end[j][1], end[j][2]))
+            if abs(got - x) > mpmath.mpf(10) ** -50:
+                return False
+    return True
+
+
 def pin_gauss_newton_quadratic() -> bool:
     """Planted root of a square random system (constant -F_p(x*) rounded to
     quad double appended to each polynomial): from x* + 1e-3 noise the
@@ -528,5 +576,6 @@ ALL_PINS = [
     pin_quadratic_form, pin_finite_differences, pin_euler_homogeneity,
     pin_cyclic_at_one, pin_cyclic_at_roots_of_unity, pin_limb_rounding, pin_abs_sums,
     pin_gauss_newton_linear, pin_gauss_newton_quadratic, pin_columns_match_rows,
-    pin_abs_sums_positive, pin_error_metric_rejects, pin_lstsq_limbs,
+    pin_abs_sums_positive, pin_error_metric_rejects, pin_lstsq_limbs, pin_homotopy_square_root,
+    pin_homotopy_decoupled_squares,
 ]

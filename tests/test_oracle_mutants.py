@@ -276,6 +276,14 @@ def _mut_abs_values_no_power(sys_, x, rows):
     return SF
 
 
+def _make_homotopy_step_sign():
+    orig = E.homotopy_step_mp
+
+    def homotopy_step_mp(sys_, X, c, wF, wc, prec=512):
+        return orig(sys_, X, c, wF, -wc, prec)  # f(x) + t c instead of f(x) - t c
+    return homotopy_step_mp
+
+
 MUTANTS = {
     "power_off_by_one": ("_power", _mut_power_off_by_one),
     "mul_sign": ("cdy_mul", _mut_mul_sign),
@@ -297,6 +305,7 @@ MUTANTS = {
     "metric_lenient": ("rel_error", _mut_rel_error_lenient),
     "lstsq_transpose_not_adjoint": ("_lstsq_householder", _mut_lstsq_transpose),
     "abs_values_no_power": ("abs_sums_values", _mut_abs_values_no_power),
+    "homotopy_sign": ("homotopy_step_mp", _make_homotopy_step_sign()),
 }
 
 
