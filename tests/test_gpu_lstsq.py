@@ -42,13 +42,27 @@ def _cond(Ab):
 
 def _check_factors(Ab, R, Q, L, pairs_qr, pairs_qq, kappa):
     """A - QR and Q^H Q - I on sampled entries, exactly from the limbs:
-    |a_ij - sum_k q_ik r_kj| <= c u sum_k |q_ik| |r_kj| and
+    |a_ij - sum_k q_ik r_kj| <= c u sum_k |q_ik| |r_kj| for j < n, y = Q^H b
+    for j = n (within c u kappa sum_i |q_ik| |b_i|: Q is orthogonal only to
+    c u kappa), and
     |sum_i conj(q_ik) q_il - delta_kl| <= c u kappa (MGS loses orthogonality
     in proportion to the condition number)."""
     N, n = Q.shape[2], Q.shape[3]
     u = UNIT[L]
     worst_qr = worst_qq = 0.0
     for i, j in pairs_qr:
+        if j == n:
+            # the right-hand side column is Q y plus a residual orthogonal to
+            # Q, so there the check is y = Q^H b: entry y_k, k = i mod n
+            k = i % n
+            acc, mag = O.ZERO, 0.0
+            for r in range(N):
+                q, bb = _exact(Q, r, k), _exact(Ab, r, n)
+                acc = O.cdy_add(acc, O.cdy_mul(O.cdy_conj(q), bb))
+                mag += O.cdy_abs_float(q) * O.cdy_abs_float(bb)
+            d = O.cdy_abs_float(O.cdy_add(_exact(R, k, n), O.cdy_neg(acc)))
+            worst_qr = max(worst_qr, d / (mag * u * kappa))
+            continue
         acc, mag = O.ZERO, 0.0
         for k in range(j + 1):
             q, r = _exact(Q, i, k), _exact(R, k, j)
@@ -110,8 +124,8 @@ def test_lstsq_large_double_double(pe):
     torch.cuda.synchronize()
     x, R, Q = x.cpu().numpy()[0], R.cpu().numpy()[0], Q.cpu().numpy()[0]
     kappa = _cond(Ab[0])
-    A = Ab[0, 0, :, :n] + 1j * Ab[0, 1, :, :n]
-    b = Ab[0, 0, :, n] + 1j * Ab[0, 1, :, n]
+    A = Ab[0, 0, 0, :, :n] + 1j * Ab[0, 1, 0, :, :n]
+    b = Ab[0, 0, 0, :, n] + 1j * Ab[0, 1, 0, :, n]
     want = np.linalg.lstsq(A, b, rcond=None)[0]
     got = x[0, 0] + 1j * x[1, 0]
     rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
