@@ -412,6 +412,157 @@ def bench_product(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------------ Newton steps
+
+def bench_newton_single(args):
+    """One Gauss-Newton step (evaluation of [J | -F], least-squares solve by
+    modified Gram-Schmidt, update) of the 256 x 256 double-double system
+    with a planted root, from the perturbed start: the step's time, beside
+    the evaluation alone."""
+    import torch
+    import oracle as O
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+
+    sys_, x = synth.workload("dd_n256")
+    planted = O.plant_root(sys_, x[0])
+    x0 = synth.perturbed_start(1, x[0])[None]
+    S = pe.System.from_sparse(planted)
+    xd = torch.from_numpy(x0).cuda()
+    ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+    resid = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K, Wm = min(args.steps, 20), min(args.warmup, 3)
+    xs = xd.clone()
+
+    def step():
+        xd.copy_(xs)  # every timed step starts from the same point
+        S.newton_step(xd, workspace=ws, resid=resid, stream=st)
+    dt, ms = _time_steps(step, K, Wm, st)
+    F = torch.empty((1, 2, 2, 256), dtype=torch.float64, device="cuda")
+    J = torch.empty((1, 2, 2, 256, 256), dtype=torch.float64, device="cuda")
+    _, ms_eval = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, Wm, st)
+    S.close()
+    # the solve's complex multiply-adds: MGS on 256 x 257 (about 2 N n^2) and
+    # back substitution
+    n = 256
+    cmadd = 2.0 * n * n * (n + 1) + n * n
+    out = line("Gauss-Newton step, complex double-double, 256 x 256 system with a planted root (evaluation, "
+               "least squares by modified Gram-Schmidt, update)", 2, sys_.n_monomials * K / dt, K, Wm, dt,
+               {"name": "newton_dd_n256", "kernel_ms": ms, "eval_ms": ms_eval,
+                "solve_complex_mult_adds": cmadd}, None, None)
+    out["metric"] = "Gauss-Newton steps/s (context)"
+    out["value"] = K / dt
+    out["unit"] = "steps/s"
+    print(json.dumps(out), flush=True)
+
+
+def bench_newton_batch(args):
+    """One batched Gauss-Newton step over the 4096 uneven systems at 8 points
+    each (every system-point solved by one workgroup), captured in a HIP
+    graph and replayed."""
+    import numpy as np
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+
+    S_count, P = BATCH_COUNT, BATCH_POINTS
+    ns = synth.batch_sizes(0, S_count)
+    dev = [pe.System.from_sparse(synth.batch_system(0, i, int(ns[i]))) for i in range(S_count)]
+    B = pe.Batch(dev)
+    rng = synth.rng_for((0, 9))
+    x = torch.from_numpy(np.concatenate([synth.unit_circle_points(rng, P, int(n), 2).reshape(-1)
+                                         for n in ns])).cuda()
+    ws = torch.empty((B.newton_workspace_bytes(P) + 7) // 8, dtype=torch.float64, device="cuda")
+    resid = torch.empty((S_count, P, 2), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    xs = x.clone()
+    B.newton_step(x, P, workspace=ws, resid=resid, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        B.newton_step(x, P, workspace=ws, resid=resid, stream=s)
+    K, Wm = min(args.steps, 3), 1
+
+    def step():
+        x.copy_(xs)
+        g.replay()
+    dt, ms = _time_steps(step, K, Wm, torch.cuda.current_stream())
+    out = line("batched Gauss-Newton step (HIP graph), complex double-double: 4096 systems, n uniform in "
+               "{32, 64, 128, 256}, 8 points each", 2, S_count * P * K / dt, K, Wm, dt,
+               {"name": "newton_batch4096", "kernel_ms": ms}, None, None)
+    out["metric"] = "system-point Gauss-Newton steps/s (context)"
+    out["unit"] = "system-point steps/s"
+    print(json.dumps(out), flush=True)
+
+
+def bench_terms_product(args):
+    """The computation of the paper's Table 1 in its own output form: the
+    value and the full gradient of each of 65,024 products of 1,024
+    variables (complex double), written per monomial (pe_eval_terms), not
+    summed into F and J."""
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+    from paper_1402_2626_amd import workmodel as W
+
+    sys_, x = synth.product_workload()
+    S = pe.System.from_sparse(sys_)
+    xd = torch.from_numpy(x).cuda()
+    V = torch.empty((1, 2, 1, sys_.n_monomials), dtype=torch.float64, device="cuda")
+    G = torch.empty((1, 2, 1, sys_.nnz), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K = min(args.steps, 50)
+    Wm = min(args.warmup, 5)
+    dt, ms = _time_steps(lambda: S.eval_terms(xd, out=(V, G), stream=st), K, Wm, st)
+    nbytes = W.bytes_per_point(sys_, want_J=True, chunks=sys_.n_polys)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = line("value and gradient of each of 65,024 products of 1,024 variables (the paper's Table 1), "
+               "complex double, per-monomial output", 1, sys_.n_monomials * K / dt, K, Wm, dt,
+               {"name": "terms_d_product_65024x1024", "kernel_ms": ms, "algorithmic_bytes": nbytes,
+                "paper_table1_ms_context": 9.10},
+               {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                "traffic": None}, None)
+    S.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_real_qd_chandrasekhar(args):
+    """Newton on Chandrasekhar's H-equation in real quad double at n = 1016
+    (the first row of the paper's Table 4: 7 iterations, evaluation on its
+    CPU), one step timed (evaluation and least squares on the GPU)."""
+    import numpy as np
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+
+    n, L = 1016, 4
+    sys_ = synth.chandrasekhar_system(n, L)
+    S = pe.System(pe.PE_REAL | L, n, sys_.poly_ptr, sys_.mon_ptr, sys_.var_idx, sys_.exps,
+                  np.ascontiguousarray(sys_.coef[:1]))
+    x0 = np.zeros((1, 1, L, n))
+    x0[0, 0, 0] = 1.0
+    xd = torch.from_numpy(x0).cuda()
+    xs = xd.clone()
+    ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+    resid = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    K, Wm = min(args.steps, 3), 1
+
+    def step():
+        xd.copy_(xs)
+        S.newton_step(xd, workspace=ws, resid=resid, stream=st)
+    dt, ms = _time_steps(step, K, Wm, st)
+    S.close()
+    out = line("Gauss-Newton step, real quad double, Chandrasekhar H-equation n = 1016 (c = 33/64)", 4,
+               K / dt, K, Wm, dt, {"name": "newton_rqd_chandrasekhar1016", "kernel_ms": ms,
+                                   "paper_table4_gpu_s_for_7_iterations_context": 59.57}, None, None)
+    out["metric"] = "Gauss-Newton steps/s (context)"
+    out["unit"] = "steps/s"
+    out["dtype"] = "f64 (quad-double real)"
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,8 +577,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run pe_autotune before timing (single systems)")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="dd_batch4096 (default, the reported line); d_n32, dd_n256, qd_n1024, "
-                         "dd_adjoint_1024x512, d_product_65024x1024, cyclic_d_n512 and cyclic_dd_n512 print "
-                         "the same kind of line for context")
+                         "dd_adjoint_1024x512, d_product_65024x1024, cyclic_d_n512, cyclic_dd_n512, "
+                         "terms_d_product_65024x1024, newton_dd_n256, newton_batch4096 and "
+                         "newton_rqd_chandrasekhar1016 print the same kind of line for context")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path (rows of F and J would shard "
@@ -444,6 +596,14 @@ def main():
         return
     if args.workload == "dd_batch4096":
         return bench_batch(args)
+    if args.workload == "newton_dd_n256":
+        return bench_newton_single(args)
+    if args.workload == "newton_batch4096":
+        return bench_newton_batch(args)
+    if args.workload == "terms_d_product_65024x1024":
+        return bench_terms_product(args)
+    if args.workload == "newton_rqd_chandrasekhar1016":
+        return bench_real_qd_chandrasekhar(args)
     if args.workload == "dd_adjoint_1024x512":
         return bench_adjoint(args)
     if args.workload == "d_product_65024x1024":

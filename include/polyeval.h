@@ -55,6 +55,15 @@ typedef int32_t pe_status;
                                  the status of the call */
 #define PE_ENONFINITE (-6)    /* non-finite values met where checked */
 
+/* Level flag for real arithmetic: a level of PE_REAL | L (L = 1, 2, 4)
+ * makes a system of real coefficients evaluated at real points in real
+ * double, double double or quad double arithmetic.  Its arrays have one
+ * component instead of two: coef [L][M], x [P][L][n], F [P][L][N],
+ * J [P][L][N][n], V [P][L][M], G [P][L][nnz].  Real systems support
+ * pe_eval, pe_eval_terms, pe_newton_step and the homotopy steps; pe_lstsq
+ * takes the same level codes. */
+#define PE_REAL 8
+
 typedef struct pe_system pe_system;
 typedef struct pe_batch pe_batch;
 
@@ -68,8 +77,9 @@ const char* pe_last_error(void);
 /* ------------------------------------------------------------------ systems
  * Load a system in sparse distributed form (Problem Statement, Sec. 1;
  * monomial split of Sec. 2.1, eq. (1)).
- *   level     1, 2 or 4 (limbs per real part); all coefficients, points and
- *             outputs of this system are at this level.
+ *   level     1, 2 or 4 (limbs per real part), or PE_REAL | 1, 2, 4 for
+ *             real arithmetic; all coefficients, points and outputs of this
+ *             system are at this level.
  *   n_vars    number of variables n (1 <= n; see the size limits below).
  *   n_polys   number of polynomials N (>= 0).
  *   poly_ptr  [N+1] int64, host: monomials of polynomial p are
@@ -79,7 +89,8 @@ const char* pe_last_error(void);
  *   var_idx   [nnz] int32, host, nnz = mon_ptr[M]: variable of each
  *             occurrence, in [0, n); distinct within a monomial (any order).
  *   exps      [nnz] int32, host: exponent of each occurrence, 1..65535.
- *   coef      [2][L][M] double, host, limb-planar coefficients.
+ *   coef      [2][L][M] double, host, limb-planar coefficients ([L][M]
+ *             for a real system).
  *   stream    stream used for the uploads (the call synchronises it).
  * Monomials with no occurrence (constants) and polynomials with no monomial
  * are allowed; duplicate monomials are kept as given (never merged).
@@ -102,7 +113,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
  * while a batch that contains the system is alive. */
 pe_status pe_system_destroy(pe_system* sys);
 
-/* Sizes of a loaded system: info[0] = level, [1] = n, [2] = N, [3] = M,
+/* Sizes of a loaded system: info[0] = level (with PE_REAL if real), [1] = n, [2] = N, [3] = M,
  * [4] = nnz, [5] = largest exponent, [6] = largest monomial size k,
  * [7] = device bytes held, [8] = chunks per workgroup of the evaluation
  * launch, [9] = LDS bytes per evaluation workgroup, [10] = segment length
@@ -144,12 +155,30 @@ pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_pe
 pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, double* J,
                   void* stream);
 
+/* Terms: the value and the gradient of every monomial, before the sum
+ * reduction into F and J (the evaluation and differentiation of products of
+ * variables of Sec. 2.2, Tables 1 and 2, with the coefficient, common factor
+ * and exponent of Sec. 2.1 and 2.3 applied).
+ *   x  device [P][2][L][n], read only.
+ *   V  device [P][2][L][M]: V[t] = c_t prod_r x_{i_r}^{d_r} for input monomial
+ *      t (the order of the create call's mon_ptr), fully overwritten.
+ *   G  device [P][2][L][nnz]: G[o] = the partial derivative of monomial t's
+ *      term with respect to its variable i_o, for input occurrence o
+ *      (mon_ptr[t] <= o < mon_ptr[t+1], the order of var_idx), fully
+ *      overwritten.  May be NULL when nnz = 0.
+ * Summing V over a polynomial's monomials gives F, and G scattered by
+ * variable gives J, up to rounding.  The first call on a system uploads a
+ * map of the input order (allocates and synchronises once, until the system
+ * is repacked or destroyed); later calls enqueue kernels only. */
+pe_status pe_eval_terms(const pe_system* sys, int32_t P, const double* x, double* V, double* G, void* stream);
+
 /* Adjoint: g = J(x)^H v at P points, without forming J (reverse mode with
  * the seed conj(v_p) per polynomial; the least-squares gradient of Sec. 1's
  * Gauss-Newton setting).
  *   x  device [P][2][L][n];  v  device [P][2][L][N];  g  device [P][2][L][n].
  * The first call with a given P may allocate a per-system workspace (kept
- * until destroy); later calls with P not above it allocate nothing. */
+ * until destroy); later calls with P not above it allocate nothing.
+ * PE_EUNSUPPORTED for a real system. */
 pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, const double* v,
                           double* g, void* stream);
 
@@ -162,7 +191,8 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
  * on the caller's stream behind one counter-reset kernel.  The systems must
  * share the level and the segment length (pe_system_set_shape; PE_EINVAL
  * otherwise) and outlive the batch: while the batch is alive they cannot be
- * repacked (pe_system_set_shape, pe_autotune) or destroyed (PE_EINVAL). */
+ * repacked (pe_system_set_shape, pe_autotune) or destroyed (PE_EINVAL).
+ * Real systems are not batched (PE_EUNSUPPORTED). */
 pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* systems, void* stream);
 pe_status pe_batch_destroy(pe_batch* batch);
 
@@ -247,7 +277,8 @@ pe_status pe_batch_newton_step(const pe_batch* batch, int32_t P, double* x_inout
  * needed (delayed normalisation: r_kj = a_k^H a_j / |a_k| and the update
  * divides by |a_k|^2); then the back substitution R x = y in stages of
  * blocks of 256 rows (eq. (4)).
- *   level      1, 2 or 4.  P points (independent problems), 0 <= P <= 65535.
+ *   level      1, 2 or 4, or PE_REAL | 1, 2, 4 (real: one component per
+ *              array below).  P points (independent problems), 0 <= P <= 65535.
  *   N, n       rows and unknowns: 1 <= n <= N <= 4096.
  *   Ab         device [P][2][L][N][n+1] row-major, column n = b; read only.
  *   x          device [P][2][L][n], the solution (written).

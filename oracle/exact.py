@@ -43,6 +43,7 @@ __all__ = [
     "max_rel_error_rows", "adjoint_exact", "adjoint_columns", "gauss_newton_step_mp",
     "system_value_at", "round_point", "speelpenning_straightforward", "plant_root",
     "abs_sums_columns", "abs_sums_values", "lstsq_limbs", "homotopy_step_mp", "homotopy_track_mp",
+    "eval_terms", "abs_terms",
 ]
 
 # --------------------------------------------------------------------------
@@ -244,6 +245,42 @@ def eval_rows(sys_, x: np.ndarray, rows: Iterable[int], want_J: bool = True):
         F[p] = f
         J[p] = jrow
     return F, J
+
+
+def eval_terms(sys_, x: np.ndarray, monomials: Iterable[int]):
+    """The terms before their sum into F and J (Sec. 2.3), for each input
+    monomial t in ``monomials`` at point x[2, L, n]: {t: (value, partials)}
+    with value = c_t prod_r x_{i_r}^{d_r} and partials[r] the derivative of
+    that term with respect to its r-th variable in the input order (the
+    order of var_idx), exactly.  The per-monomial output of products of
+    variables and their gradients (Sec. 2.2, Tables 1 and 2)."""
+    X = point_from_limbs(x)
+    out = {}
+    for t in monomials:
+        vs, ds = sys_.monomial(int(t))
+        out[int(t)] = monomial_value_and_partials(_coef(sys_, int(t)), [X[int(v)] for v in vs], ds)
+    return out
+
+
+def abs_terms(sys_, x: np.ndarray, monomials: Iterable[int]):
+    """Normalisers of the terms' error metric (float64): {t: (|c| prod |x|^d,
+    [|c| d_r |x_r|^(d_r - 1) prod_{s != r} |x_s|^d_s])}."""
+    ax = np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+    out = {}
+    for t in monomials:
+        vs, ds = sys_.monomial(int(t))
+        ac = float(np.hypot(sys_.coef[0, :, int(t)].sum(), sys_.coef[1, :, int(t)].sum()))
+        pw = [float(ax[int(v)]) ** int(d) for v, d in zip(vs, ds)]
+        val = ac * math.prod(pw)
+        parts = []
+        for r, (v, d) in enumerate(zip(vs, ds)):
+            g = ac * int(d) * float(ax[int(v)]) ** (int(d) - 1)
+            for q in range(len(vs)):
+                if q != r:
+                    g *= pw[q]
+            parts.append(g)
+        out[int(t)] = (val, parts)
+    return out
 
 
 def eval_columns(sys_, x: np.ndarray, cols: Iterable[int]):

@@ -25,6 +25,9 @@ ARCH = os.environ.get("PE_OFFLOAD_ARCH", "gfx950")
 
 LEVELS = (1, 2, 4)
 KINDS = (0, 1, 2, 3, 4)  # rows, adjoint, batch, Gauss-Newton, least squares
+# real-arithmetic level codes (8 | limbs) and the kinds compiled for them
+REAL_LEVELS = (9, 10, 12)
+REAL_KINDS = (0, 3, 4)
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,16 +41,17 @@ def compile_commands(objdir):
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmds.append((obj, [HIPCC, *FLAGS, "-c", *lang, os.path.join(CSRC, src), "-o", obj]))
-    for L in LEVELS:
-        for K in KINDS:
-            obj = os.path.join(objdir, f"instances_L{L}_K{K}.o")
-            cmds.append((obj, [HIPCC, *FLAGS, f"-DPE_LEVEL={L}", f"-DPE_KIND={K}", "-c",
-                               os.path.join(CSRC, "instances.hip"), "-o", obj]))
+    pairs = [(L, K) for L in LEVELS for K in KINDS] + [(L, K) for L in REAL_LEVELS for K in REAL_KINDS]
+    for L, K in pairs:
+        obj = os.path.join(objdir, f"instances_L{L}_K{K}.o")
+        cmds.append((obj, [HIPCC, *FLAGS, f"-DPE_LEVEL={L}", f"-DPE_KIND={K}", "-c",
+                           os.path.join(CSRC, "instances.hip"), "-o", obj]))
     return cmds
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
-    jobs = jobs or min(len(LEVELS) * len(KINDS) + 2, max(1, os.cpu_count() or 1), 16)
+    jobs = jobs or min(len(LEVELS) * len(KINDS) + len(REAL_LEVELS) * len(REAL_KINDS) + 2,
+                       max(1, os.cpu_count() or 1), 16)
     objdir = tempfile.mkdtemp(prefix="pe_build_")
     try:
         cmds = compile_commands(objdir)

@@ -38,7 +38,9 @@
 
 namespace pe {
 
-enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2 };
+// EVAL: F and J; FONLY: F; ADJ: J^H v; TERMS: every monomial's value and
+// partial derivatives, unsummed, in the input order
+enum : int { MODE_EVAL = 0, MODE_FONLY = 1, MODE_ADJ = 2, MODE_TERMS = 3 };
 
 struct SysView {
   int n, N;
@@ -54,6 +56,18 @@ struct SysView {
   const uint16_t* colptr;
   const uint32_t* row_order;  // [N] rows in decreasing cost (workgroup b of a
                               // point takes row row_order[b]), or null: row b
+  const uint32_t* occ_orig;   // like occ: input index of each record's occurrence
+  const uint32_t* mon_orig;   // [M] input index of each packed monomial
+};
+
+// destinations of the TERMS mode at one point: the value of input monomial t
+// at V[t] (planes v_plane apart), the partial derivative of input occurrence
+// o at G[o] (planes g_plane apart)
+struct TermsOut {
+  double* V = nullptr;
+  int64_t v_plane = 0;
+  double* G = nullptr;
+  int64_t g_plane = 0;
 };
 
 // output addressing: element (pt, c, l, row, col) of J is at
@@ -68,56 +82,64 @@ struct OutView {
 
 // ------------------------------------------------------------------ helpers
 
+// A level-L number (level code L: complex or real, see mdarith.hpp) in a
+// planar array: limb l of the real part at base[l * plane + idx], of the
+// imaginary part at base[(limbs + l) * plane + idx].
 template <int L>
 __device__ __forceinline__ C<L> load_planar(const double* __restrict__ base, int64_t plane, int64_t idx) {
+  constexpr int NL = limbs_of(L);
   C<L> r;
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < NL; ++l) {
     r.re.x[l] = base[l * plane + idx];
-    r.im.x[l] = base[(L + l) * plane + idx];
+    if constexpr (!is_real(L)) r.im.x[l] = base[(NL + l) * plane + idx];
   }
   return r;
 }
 
 template <int L>
 __device__ __forceinline__ void store_planar(double* __restrict__ base, int64_t plane, int64_t idx, const C<L>& v) {
+  constexpr int NL = limbs_of(L);
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < NL; ++l) {
     base[l * plane + idx] = v.re.x[l];
-    base[(L + l) * plane + idx] = v.im.x[l];
+    if constexpr (!is_real(L)) base[(NL + l) * plane + idx] = v.im.x[l];
   }
 }
 
+// one number as consecutive doubles: real limbs, then imaginary limbs
 template <int L>
 __device__ __forceinline__ C<L> load_aos(const double* p) {
+  constexpr int NL = limbs_of(L);
   C<L> r;
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < NL; ++l) {
     r.re.x[l] = p[l];
-    r.im.x[l] = p[L + l];
+    if constexpr (!is_real(L)) r.im.x[l] = p[NL + l];
   }
   return r;
 }
 
 template <int L>
 __device__ __forceinline__ void store_aos(double* p, const C<L>& v) {
+  constexpr int NL = limbs_of(L);
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < NL; ++l) {
     p[l] = v.re.x[l];
-    p[L + l] = v.im.x[l];
+    if constexpr (!is_real(L)) p[NL + l] = v.im.x[l];
   }
 }
 
-// LDS arrays of complex multi-doubles.  D and DD are planar (component k of
-// element i at base[k * stride + i], components re limbs then im limbs): a
+// LDS arrays of multi-doubles.  D and DD are planar (component k of element
+// i at base[k * stride + i], components re limbs then im limbs): a
 // wavefront's gather then reads 8-byte words spread over all banks, where
 // 16- or 32-byte records map every lane's access onto a fraction of them.
-// QD keeps one 64-byte record per element (base[i * 8 + k]), which moves the
-// same bytes in half as many LDS instructions and measured faster.
+// Complex QD keeps one 64-byte record per element (base[i * 8 + k]), which
+// moves the same bytes in half as many LDS instructions and measured faster.
 template <int L>
 __device__ __forceinline__ C<L> lds_ld(const double* base, int stride, int i) {
   if constexpr (L == 4)
-    return load_aos<L>(base + size_t(i) * (2 * L));
+    return load_aos<L>(base + size_t(i) * width_of(L));
   else
     return load_planar<L>(base, stride, i);
 }
@@ -125,7 +147,7 @@ __device__ __forceinline__ C<L> lds_ld(const double* base, int stride, int i) {
 template <int L>
 __device__ __forceinline__ void lds_st(double* base, int stride, int i, const C<L>& v) {
   if constexpr (L == 4)
-    store_aos(base + size_t(i) * (2 * L), v);
+    store_aos(base + size_t(i) * width_of(L), v);
   else
     store_planar(base, stride, i, v);
 }
@@ -134,9 +156,9 @@ template <int L>
 __device__ __forceinline__ C<L> shfl_xor_c(const C<L>& v, int mask) {
   C<L> r;
 #pragma unroll
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < limbs_of(L); ++l) {
     r.re.x[l] = __shfl_xor(v.re.x[l], mask);
-    r.im.x[l] = __shfl_xor(v.im.x[l], mask);
+    if constexpr (!is_real(L)) r.im.x[l] = __shfl_xor(v.im.x[l], mask);
   }
   return r;
 }
@@ -165,7 +187,7 @@ __device__ __forceinline__ int tab_cols(const SysView& S) { return S.n + 1; }
 // 2L planes of n + 1 doubles
 template <int L>
 __device__ __forceinline__ const double* tab_block(const SysView& S, const double* tab, int e) {
-  return tab + size_t(e - S.tab_first) * (2 * L) * tab_cols(S);
+  return tab + size_t(e - S.tab_first) * width_of(L) * tab_cols(S);
 }
 
 // the table holds x itself and every power a common factor needs
@@ -238,6 +260,7 @@ struct ChunkLoads {
   C<L> coef;         // coefficient on lane 0 of a monomial's group, else 1
   C<L> vp;           // adjoint weight v_p of the chunk's polynomial
   int cb[CPL], ce[CPL];  // slot ranges of the lane's owned columns
+  uint32_t orig[SEG];    // input occurrence of each record (TERMS mode only)
 };
 
 // the lane's loads for the chunk with descriptor `cd` (act false: no chunk)
@@ -254,7 +277,7 @@ __device__ __forceinline__ void load_chunk_of(const SysView& S, const ChunkDesc&
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     const int c = lt + cc * kSub;
-    const bool use = MODE != MODE_FONLY && act && c < S.n;
+    const bool use = MODE != MODE_FONLY && MODE != MODE_TERMS && act && c < S.n;
     cl.cb[cc] = use ? int(S.colptr[cd.colptr_base + c]) : 0;
     cl.ce[cc] = use ? int(S.colptr[cd.colptr_base + c + 1]) : 0;
   }
@@ -262,7 +285,7 @@ __device__ __forceinline__ void load_chunk_of(const SysView& S, const ChunkDesc&
   const int g = lt / s;
   const int q = lt & (s - 1);
   const bool active = g < int(cd.count);
-  cl.coef = (active && q == 0) ? load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * (2 * L)) : c_one<L>();
+  cl.coef = (active && q == 0) ? load_aos<L>(S.mcoef + size_t(cd.mon_base + g) * width_of(L)) : c_one<L>();
   if (MODE == MODE_ADJ) cl.vp = act ? load_planar<L>(vpt, S.N, cd.poly) : c_zero<L>();
   // lanes past the chunk's last group get neutral records; records are
   // moved as 64-bit words (var | exp << 16 | slot << 32)
@@ -278,6 +301,8 @@ __device__ __forceinline__ void load_chunk_of(const SysView& S, const ChunkDesc&
     cl.rec[i].exp = uint16_t(r >> 16);
     cl.rec[i].slot = uint16_t(r >> 32);
     cl.rec[i].pad = 0;
+    if (MODE == MODE_TERMS)
+      cl.orig[i] = in_chunk ? S.occ_orig[cd.occ_base + size_t(min(i, max(segc - 1, 0))) * cd.width + lt] : kNoOcc;
   }
 }
 
@@ -298,12 +323,16 @@ __device__ __forceinline__ void load_chunk(const SysView& S, uint32_t ch, bool a
 // compensated sums, the double-double additions) accepts.
 template <int L>
 __device__ __forceinline__ C<L> scale_by_exponent(const C<L>& a, double d) {
-  if constexpr (L == 2) {
-    C<2> r;
-    r.re.x[0] = a.re.x[0] * d;
-    r.re.x[1] = PE_FMA(a.re.x[1], d, PE_FMA(a.re.x[0], d, -r.re.x[0]));
-    r.im.x[0] = a.im.x[0] * d;
-    r.im.x[1] = PE_FMA(a.im.x[1], d, PE_FMA(a.im.x[0], d, -r.im.x[0]));
+  if constexpr (limbs_of(L) == 2) {
+    auto scale = [d](const R<2>& v) {
+      R<2> r;
+      r.x[0] = v.x[0] * d;
+      r.x[1] = PE_FMA(v.x[1], d, PE_FMA(v.x[0], d, -r.x[0]));
+      return r;
+    };
+    C<L> r;
+    r.re = scale(a.re);
+    if constexpr (!is_real(L)) r.im = scale(a.im);
     return r;
   } else {
     return c_mul_d(a, d);
@@ -337,7 +366,7 @@ __device__ __forceinline__ C<L> cf_factor_full(const SysView& S, const double* t
 template <int L, int SEG, int CPL, int MODE, bool FAST, bool POW = true, bool GX = false>
 __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
                                                      const double* __restrict__ xpt, const double* tab,
-                                                     double* contrib, C<L>& facc) {
+                                                     double* contrib, C<L>& facc, const TermsOut& to) {
   const ChunkDesc& cd = cl.cd;
   const int s = cd.s;
   const int g = lt / s;
@@ -404,45 +433,54 @@ __device__ __forceinline__ void chunk_monomials_body(const SysView& S, const Chu
     if (active && q == 0) facc = c_add(facc, B);
     return;
   }
-  // reverse sweep of Speelpenning's product over the segment
+  // reverse sweep of Speelpenning's product over the segment; a partial
+  // goes to its LDS slot, or in TERMS mode to its input position
+  auto put = [&](int i, const C<L>& gval) {
+    if constexpr (MODE == MODE_TERMS) {
+      if (cl.orig[i] != kNoOcc) store_planar(to.G, to.g_plane, cl.orig[i], gval);
+    } else {
+      lds_st(contrib, ms, cl.rec[i].slot, gval);
+    }
+  };
   C<L> Sx = (s > 1) ? c_mul(cf, E) : cf;
 #pragma unroll
   for (int i = SEG - 1; i >= 1; --i) {
     if (FAST || i < segc) {
       C<L> gi = c_mul(pre[i - 1], Sx);
       Sx = c_mul(Sx, xv[i]);
-      lds_st(contrib, ms, cl.rec[i].slot, POW ? scale_by_exponent(gi, double(cl.rec[i].exp)) : gi);
+      put(i, POW ? scale_by_exponent(gi, double(cl.rec[i].exp)) : gi);
     }
   }
   if (FAST || segc >= 1) {
     C<L> g0 = Sx;
     Sx = c_mul(Sx, xv[0]);
-    lds_st(contrib, ms, cl.rec[0].slot, POW ? scale_by_exponent(g0, double(cl.rec[0].exp)) : g0);
+    put(0, POW ? scale_by_exponent(g0, double(cl.rec[0].exp)) : g0);
   }
   if (MODE == MODE_EVAL && active && q == 0) facc = c_add(facc, Sx);
+  if (MODE == MODE_TERMS && active && q == 0) store_planar(to.V, to.v_plane, S.mon_orig[cd.mon_base + g], Sx);
 }
 
 template <int L, int SEG, int CPL, int MODE>
 __device__ __forceinline__ void chunk_monomials(const SysView& S, const ChunkLoads<L, SEG, CPL>& cl, int lt,
                                                 const double* __restrict__ xpt, const double* tab,
-                                                double* contrib, C<L>& facc) {
+                                                double* contrib, C<L>& facc, const TermsOut& to = TermsOut{}) {
   // a wavefront whose lanes all lie past the chunk's last monomial has
   // nothing to contribute (its records are all neutral)
   if (__builtin_amdgcn_readfirstlane(lt & ~63) >= int(cl.cd.width)) return;
   if (int(cl.cd.seg) == SEG && tab_full(S)) {
     if (S.emax >= 2)
-      chunk_monomials_body<L, SEG, CPL, MODE, true, true>(S, cl, lt, xpt, tab, contrib, facc);
+      chunk_monomials_body<L, SEG, CPL, MODE, true, true>(S, cl, lt, xpt, tab, contrib, facc, to);
     else
-      chunk_monomials_body<L, SEG, CPL, MODE, true, false>(S, cl, lt, xpt, tab, contrib, facc);
+      chunk_monomials_body<L, SEG, CPL, MODE, true, false>(S, cl, lt, xpt, tab, contrib, facc, to);
     return;
   }
-  if constexpr (L == 1) {
+  if constexpr (limbs_of(L) == 1) {
     if (int(cl.cd.seg) == SEG && S.emax == 1 && tab_entries(S) == 0) {
-      chunk_monomials_body<L, SEG, CPL, MODE, true, false, true>(S, cl, lt, xpt, tab, contrib, facc);
+      chunk_monomials_body<L, SEG, CPL, MODE, true, false, true>(S, cl, lt, xpt, tab, contrib, facc, to);
       return;
     }
   }
-  chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc);
+  chunk_monomials_body<L, SEG, CPL, MODE, false>(S, cl, lt, xpt, tab, contrib, facc, to);
 }
 
 // Double-double column sum: compensated summation (Ogita, Rump and Oishi's
@@ -486,15 +524,18 @@ __device__ __forceinline__ void dd_sum_slots(double& hi, double& lo, const doubl
 template <int L, int CPL>
 __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&ce)[CPL], const double* contrib,
                                              int ms, C<L> (&acc)[CPL]) {
-  if constexpr (L == 2) {
+  if constexpr (limbs_of(L) == 2) {
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       if (cb[cc] >= ce[cc]) continue;
-      double rh = acc[cc].re.x[0], rl = acc[cc].re.x[1], ih = acc[cc].im.x[0], il = acc[cc].im.x[1];
+      double rh = acc[cc].re.x[0], rl = acc[cc].re.x[1];
       dd_sum_slots(rh, rl, contrib, contrib + ms, cb[cc], ce[cc]);
-      dd_sum_slots(ih, il, contrib + 2 * ms, contrib + 3 * ms, cb[cc], ce[cc]);
       two_sum(rh, rl, acc[cc].re.x[0], acc[cc].re.x[1]);
-      two_sum(ih, il, acc[cc].im.x[0], acc[cc].im.x[1]);
+      if constexpr (!is_real(L)) {
+        double ih = acc[cc].im.x[0], il = acc[cc].im.x[1];
+        dd_sum_slots(ih, il, contrib + 2 * ms, contrib + 3 * ms, cb[cc], ce[cc]);
+        two_sum(ih, il, acc[cc].im.x[0], acc[cc].im.x[1]);
+      }
     }
     return;
   }
@@ -516,29 +557,36 @@ __device__ __forceinline__ void chunk_owners(const int (&cb)[CPL], const int (&c
 // result as its F partial (fpart[w], planar with plane stride kMaxWaves)
 constexpr int kMaxWaves = 16;
 
+// Sum of a value over groups of SPAN neighbouring lanes (SPAN a power of two
+// up to 64) by an XOR butterfly; every lane of a group gets the same sum.
+// Double-double: TwoSum on the high parts, low parts and errors in a plain
+// sum, renormalized once (the compensated summation of the owners).
+template <int L, int SPAN>
+__device__ __forceinline__ C<L> lane_group_sum(const C<L>& v) {
+  C<L> f = v;
+  if constexpr (limbs_of(L) == 2) {
+    auto sum = [](R<2>& x) {
+      double h = x.x[0], l = x.x[1];
+      for (int m = 1; m < SPAN; m <<= 1) {
+        const double oh = __shfl_xor(h, m), ol = __shfl_xor(l, m);
+        double s, e;
+        two_sum(h, oh, s, e);
+        h = s;
+        l = (l + ol) + e;
+      }
+      two_sum(h, l, x.x[0], x.x[1]);
+    };
+    sum(f.re);
+    if constexpr (!is_real(L)) sum(f.im);
+  } else {
+    for (int m = 1; m < SPAN; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
+  }
+  return f;
+}
+
 template <int L>
 __device__ __forceinline__ void store_wave_f(const C<L>& facc, double* fpart) {
-  C<L> f = facc;
-  if constexpr (L == 2) {
-    // double-double: TwoSum on the high parts, low parts and errors in a
-    // plain sum, renormalized once (the compensated summation of the owners)
-    double rh = f.re.x[0], rl = f.re.x[1], ih = f.im.x[0], il = f.im.x[1];
-    for (int m = 1; m < 64; m <<= 1) {
-      const double orh = __shfl_xor(rh, m), orl = __shfl_xor(rl, m);
-      const double oih = __shfl_xor(ih, m), oil = __shfl_xor(il, m);
-      double s, e;
-      two_sum(rh, orh, s, e);
-      rh = s;
-      rl = (rl + orl) + e;
-      two_sum(ih, oih, s, e);
-      ih = s;
-      il = (il + oil) + e;
-    }
-    two_sum(rh, rl, f.re.x[0], f.re.x[1]);
-    two_sum(ih, il, f.im.x[0], f.im.x[1]);
-  } else {
-    for (int m = 1; m < 64; m <<= 1) f = c_add(f, shfl_xor_c(f, m));
-  }
+  const C<L> f = lane_group_sum<L, 64>(facc);
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64);
   if ((threadIdx.x & 63) == 0) lds_st(fpart, kMaxWaves, w, f);
 }
@@ -555,16 +603,17 @@ template <int L, int SEG, int CPL, int G, int MODE>
 __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1,
                                                const double* __restrict__ xpt, const double* __restrict__ vpt,
                                                const double* tab, double* contrib_base, C<L> (&acc)[CPL],
-                                               double* fpart, ChunkLoads<L, SEG, CPL>& cl) {
+                                               double* fpart, ChunkLoads<L, SEG, CPL>& cl,
+                                               const TermsOut& to = TermsOut{}) {
   const int sg = sub_group();
   const int lt = int(threadIdx.x) - sg * kSub;
-  double* contrib = contrib_base + size_t(sg) * S.max_slots * 2 * L;
+  double* contrib = contrib_base + size_t(sg) * S.max_slots * width_of(L);
   C<L> facc = c_zero<L>();
   if (MODE != MODE_ADJ && fpart && ch0 >= ch1) store_wave_f(facc, fpart);
   for (uint32_t base = ch0; base < ch1; base += G) {
-    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib, facc);
+    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib, facc, to);
     if (MODE != MODE_ADJ && fpart && base + G >= ch1) store_wave_f(facc, fpart);
-    if (MODE == MODE_FONLY) {
+    if (MODE == MODE_FONLY || MODE == MODE_TERMS) {
       if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
       continue;
     }
@@ -579,7 +628,7 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
     // in flight meanwhile), D after the barrier (its four-chunk kernels have
     // no registers to spare across it), QD, whose registers are already
     // spilled to the accumulation registers, after the owners add
-    constexpr int kWhen = L == 2 ? 0 : (L == 1 ? 1 : 2);
+    constexpr int kWhen = limbs_of(L) == 2 ? 0 : (limbs_of(L) == 1 ? 1 : 2);
     if (kWhen == 0 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
     __syncthreads();
     if (kWhen == 1 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
@@ -594,11 +643,11 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
 template <int L>
 __host__ __device__ inline size_t lds_bytes(int n, int tab_first, int tab_last, int max_slots, int G) {
   const size_t tab = tab_last >= tab_first ? size_t(tab_last - tab_first + 1) * (n + 1) : 0;
-  return (tab + size_t(G) * max_slots + kMaxWaves) * 2 * L * sizeof(double);
+  return (tab + size_t(G) * max_slots + kMaxWaves) * width_of(L) * sizeof(double);
 }
 
 __device__ __forceinline__ size_t tab_doubles(const SysView& S, int L) {
-  return size_t(tab_entries(S)) * tab_cols(S) * 2 * L;
+  return size_t(tab_entries(S)) * tab_cols(S) * width_of(L);
 }
 
 // Write row p of J and F (EVAL / FONLY).  F: the first thread of the last
@@ -615,7 +664,7 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
-      if (c < S.n) lds_st(scratch + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
+      if (c < S.n) lds_st(scratch + size_t(sg - 1) * width_of(L) * S.n, S.n, c, acc[cc]);
     }
   }
   __syncthreads();
@@ -625,7 +674,7 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           const int c = lt + cc * kSub;
-          if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(scratch + size_t(o - 1) * (2 * L) * S.n, S.n, c));
+          if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(scratch + size_t(o - 1) * width_of(L) * S.n, S.n, c));
         }
       }
     }
@@ -660,7 +709,7 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   const double* xpt = x + pt * x_pt;
   double* tab = lds;
   double* contrib = lds + tab_doubles(S, L);
-  double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
+  double* fpart = contrib + size_t(G) * S.max_slots * width_of(L);
   // loads first, in the order they are needed: x for the table, the row's
   // first chunk descriptors (row-ordered copy, no dependence on chunk_ptr),
   // then the lane's records; the table is built while they are in flight
@@ -675,8 +724,19 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
-  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+  if constexpr (MODE == MODE_TERMS) {
+    // values and partials go straight to their input positions: O.F and
+    // O.J hold the V and G arrays
+    TermsOut to;
+    to.V = O.F + pt * O.f_pt;
+    to.v_plane = O.f_plane;
+    to.G = O.J + pt * O.j_pt;
+    to.g_plane = O.j_plane;
+    process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, nullptr, cl, to);
+  } else {
+    process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
+    write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+  }
 }
 
 // Adjoint: grid P * NG workgroups of G * 256 threads; group gi covers
@@ -715,7 +775,7 @@ __global__ __launch_bounds__(G * kSub) void adjoint_rows_kernel(SysView S, const
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         const int c = lt + cc * kSub;
-        if (c < S.n) lds_st(contrib + size_t(sg - 1) * (2 * L) * S.n, S.n, c, acc[cc]);
+        if (c < S.n) lds_st(contrib + size_t(sg - 1) * width_of(L) * S.n, S.n, c, acc[cc]);
       }
     }
     __syncthreads();
@@ -724,11 +784,11 @@ __global__ __launch_bounds__(G * kSub) void adjoint_rows_kernel(SysView S, const
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         const int c = lt + cc * kSub;
-        if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(contrib + size_t(o - 1) * (2 * L) * S.n, S.n, c));
+        if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(contrib + size_t(o - 1) * width_of(L) * S.n, S.n, c));
       }
     }
   }
-  double* out = part + size_t(pt * NG + gi) * 2 * L * S.n;
+  double* out = part + size_t(pt * NG + gi) * width_of(L) * S.n;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     const int c = lt + cc * kSub;
@@ -744,8 +804,8 @@ __global__ void adjoint_reduce_kernel(int n, int NG, int P, const double* __rest
   const int pt = int(idx / n);
   const int j = int(idx - int64_t(pt) * n);
   C<L> s = c_zero<L>();
-  for (int gi = 0; gi < NG; ++gi) s = c_add(s, load_planar<L>(part + size_t(pt * NG + gi) * 2 * L * n, n, j));
-  store_planar(g + size_t(pt) * 2 * L * n, n, j, c_conj(s));
+  for (int gi = 0; gi < NG; ++gi) s = c_add(s, load_planar<L>(part + size_t(pt * NG + gi) * width_of(L) * n, n, j));
+  store_planar(g + size_t(pt) * width_of(L) * n, n, j, c_conj(s));
 }
 
 // ------------------------------------------------------------------ batches
@@ -794,7 +854,7 @@ __global__ __launch_bounds__(G * kSub) void batch_rows_kernel(const SysView* __r
       O.J = out.J + out.J_off[s] * P;
       O.j_row = ld;
       O.j_plane = int64_t(N) * ld;
-      O.j_pt = 2 * L * O.j_plane;
+      O.j_pt = width_of(L) * O.j_plane;
       O.F = O.J + n;
       O.f_row = ld;
       O.f_plane = O.j_plane;
@@ -804,16 +864,16 @@ __global__ __launch_bounds__(G * kSub) void batch_rows_kernel(const SysView* __r
       O.J = out.J ? out.J + out.J_off[s] * P : nullptr;
       O.j_row = n;
       O.j_plane = int64_t(N) * n;
-      O.j_pt = 2 * L * O.j_plane;
+      O.j_pt = width_of(L) * O.j_plane;
       O.F = out.F + out.F_off[s] * P;
       O.f_row = 1;
       O.f_plane = N;
-      O.f_pt = 2 * L * int64_t(N);
+      O.f_pt = width_of(L) * int64_t(N);
       O.f_sign = 1.0;
     }
     double* tab = lds;
     double* contrib = lds + tab_doubles(S, L);
-    double* fpart = contrib + size_t(G) * S.max_slots * 2 * L;
+    double* fpart = contrib + size_t(G) * S.max_slots * width_of(L);
     const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
     const bool resident = ch1 - ch0 <= uint32_t(G);
     ChunkLoads<L, SEG, CPL> cl;
@@ -821,19 +881,137 @@ __global__ __launch_bounds__(G * kSub) void batch_rows_kernel(const SysView* __r
     const double* xs = x + x_off[s] * P;
     C<L> x0 = table_first_x<L>(S, xs);
     for (int pt = 0; pt < P; ++pt) {
-      const double* xpt = xs + int64_t(pt) * 2 * L * n;
+      const double* xpt = xs + int64_t(pt) * width_of(L) * n;
       if (!resident) load_chunk<L, SEG, CPL, MODE>(S, ch0 + sg, ch0 + sg < ch1, lt, nullptr, cl);
       // the previous point's write_row is done with the LDS before any
       // thread passes this barrier
       build_power_table<L, G * kSub>(S, xpt, tab, x0);
       __syncthreads();
       // the next point's first table column is loaded while this one runs
-      if (pt + 1 < P) x0 = table_first_x<L>(S, xpt + 2 * L * n);
+      if (pt + 1 < P) x0 = table_first_x<L>(S, xpt + width_of(L) * n);
       C<L> acc[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
       process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
       write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+    }
+  }
+}
+
+
+// Output view of batch system s (the evaluation layout, or the augmented
+// Newton matrices [J | -F] with row stride n + 1)
+template <int L>
+__device__ __forceinline__ OutView batch_out_view(const BatchOut& out, int s, int n, int N, int P) {
+  OutView O;
+  if (out.newton) {
+    const int64_t ld = n + 1;
+    O.J = out.J + out.J_off[s] * P;
+    O.j_row = ld;
+    O.j_plane = int64_t(N) * ld;
+    O.j_pt = width_of(L) * O.j_plane;
+    O.F = O.J + n;
+    O.f_row = ld;
+    O.f_plane = O.j_plane;
+    O.f_pt = O.j_pt;
+    O.f_sign = -1.0;
+  } else {
+    O.J = out.J ? out.J + out.J_off[s] * P : nullptr;
+    O.j_row = n;
+    O.j_plane = int64_t(N) * n;
+    O.j_pt = width_of(L) * O.j_plane;
+    O.F = out.F + out.F_off[s] * P;
+    O.f_row = 1;
+    O.f_plane = N;
+    O.f_pt = width_of(L) * int64_t(N);
+    O.f_sign = 1.0;
+  }
+  return O;
+}
+
+// Persistent kernel for small rows: systems whose rows are at most one chunk
+// of at most VW lanes and that have at most VW variables.  The 256 threads of
+// a workgroup hold Q = 256 / VW copies of the row, copy q (threads
+// q VW .. q VW + VW - 1) at point pt0 + q, so that Q points are evaluated in
+// one pass instead of one point per 256 lanes.  Each copy has its own power
+// table, slot region and F partials in LDS; lane v of a copy does what lane
+// v of a one-chunk workgroup of eval_rows_kernel does (the same records, the
+// same monomial phase, the same owner column v), so every row equals
+// pe_eval's bit for bit.  The records are loaded once per row.  Every
+// workgroup reaches the exit test after every item, so the grid drains.
+template <int L, int SEG, int VW, int MODE>
+__global__ __launch_bounds__(kSub, 2) void batch_small_kernel(const SysView* __restrict__ views,
+                                                              const uint64_t* __restrict__ items, int64_t nitems,
+                                                              int* counter, int P, const double* __restrict__ x,
+                                                              const int64_t* __restrict__ x_off, BatchOut out) {
+  static_assert(VW == 32 || VW == 64 || VW == 128 || VW == 256, "copy width");
+  constexpr int Q = kSub / VW;
+  constexpr int WPC = VW >= 64 ? VW / 64 : 1;  // F partials per copy (wavefront parts)
+  extern __shared__ double lds[];
+  __shared__ int64_t item_sh;
+  const int qi = int(threadIdx.x) / VW;
+  const int lv = int(threadIdx.x) - qi * VW;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int64_t it = item_sh;
+    __syncthreads();
+    if (it >= nitems) break;
+    const uint64_t w = items[it];
+    const int s = int(w >> 32);
+    const int p = int(w & 0xffffffffu);
+    const SysView S = views[s];
+    const int n = S.n, N = S.N;
+    const OutView O = batch_out_view<L>(out, s, n, N, P);
+    // copy qi's LDS: [table][slots][F partials]
+    const size_t per_copy = tab_doubles(S, L) + size_t(S.max_slots) * width_of(L) + size_t(WPC) * width_of(L);
+    double* tab = lds + per_copy * qi;
+    double* contrib = tab + tab_doubles(S, L);
+    double* fpart = contrib + size_t(S.max_slots) * width_of(L);
+    const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
+    ChunkLoads<L, SEG, 1> cl;
+    load_chunk<L, SEG, 1, MODE>(S, ch0, ch0 < ch1, lv, nullptr, cl);
+    const double* xs = x + x_off[s] * P;
+    for (int pt0 = 0; pt0 < P; pt0 += Q) {
+      const int pt = pt0 + qi;
+      const bool live = pt < P;
+      const double* xpt = xs + int64_t(live ? pt : 0) * width_of(L) * n;
+      // the power table of copy qi (the previous pass's owners and writes
+      // are done with the LDS before any thread passes the barrier below)
+      if (tab_entries(S) > 0) {
+        for (int v = lv; v <= n; v += VW) {
+          const C<L> x1 = v < n ? load_planar<L>(xpt, n, v) : c_one<L>();
+          C<L> pw = x1;
+          for (int e = 1; e <= S.tab_last; ++e) {
+            if (e > 1) pw = c_mul(pw, x1);
+            if (e >= S.tab_first) lds_st(const_cast<double*>(tab_block<L>(S, tab, e)), tab_cols(S), v, pw);
+          }
+        }
+      }
+      __syncthreads();
+      C<L> facc = c_zero<L>();
+      if (ch0 < ch1) chunk_monomials<L, SEG, 1, MODE>(S, cl, lv, xpt, tab, contrib, facc);
+      // F partial of each wavefront part of the copy (lanes of one copy
+      // only; the order is that of store_wave_f, lanes of other copies
+      // excluded)
+      {
+        constexpr int span = VW < 64 ? VW : 64;
+        const C<L> f = lane_group_sum<L, span>(facc);
+        if ((lv & (span - 1)) == 0) lds_st(fpart, WPC, lv / span, f);
+      }
+      __syncthreads();
+      if (MODE == MODE_EVAL) {
+        C<L> acc[1] = {c_zero<L>()};
+        int cb[1] = {cl.cb[0]}, ce[1] = {cl.ce[0]};
+        chunk_owners<L, 1>(cb, ce, contrib, S.max_slots, acc);
+        if (live && lv < n) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, lv, acc[0]);
+      }
+      if (live && lv == 0) {
+        C<L> F = lds_ld<L>(fpart, WPC, 0);
+        for (int o = 1; o < WPC; ++o) F = c_add(F, lds_ld<L>(fpart, WPC, o));
+        if (O.f_sign < 0) F = c_neg(F);
+        store_planar(O.F + pt * O.f_pt + int64_t(p) * O.f_row, O.f_plane, 0, F);
+      }
     }
   }
 }

@@ -1,5 +1,6 @@
 // Instances of the kernel launchers of launch.hpp for one level and one kind,
-// chosen at compile time: PE_LEVEL (1, 2 or 4) and PE_KIND (0 rows, 1 adjoint,
+// chosen at compile time: PE_LEVEL (a level code: 1, 2 or 4, or 8 | 1, 2, 4
+// for real numbers) and PE_KIND (0 rows, 1 adjoint,
 // 2 batch, 3 Gauss-Newton in one workgroup, 4 column-parallel least squares).
 // The build compiles this file once per pair.
 #define PE_LAUNCH_DEFINITIONS

@@ -49,6 +49,7 @@ struct EvalShape {
 // one persistent launch over the items of a batch class
 struct BatchShape {
   int seg = 4, G = 1, cpl = 1;
+  int vw = 0;  // copy width of batch_small_kernel, 0: batch_rows_kernel
   size_t lds = 0;
   int64_t nitems = 0;
   const uint64_t* items = nullptr;
@@ -104,13 +105,14 @@ hipError_t launch_rows_t(const EvalShape& sh, int P, const double* x, const OutV
   if (e != hipSuccess) return e;
   const int64_t blocks = int64_t(P) * sh.view.N;
   hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), sh.lds, st, sh.view, O, x,
-                     int64_t(2) * L * sh.view.n);
+                     int64_t(width_of(L)) * sh.view.n);
   return hipGetLastError();
 }
 
 template <int L, int SEG, int G>
 hipError_t rows_lsg(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st) {
   const int cpl = sh.cpl;
+  if (mode == MODE_TERMS) return launch_rows_t<L, SEG, 1, G, MODE_TERMS>(sh, P, x, O, st);
   if (mode == MODE_EVAL) {
     if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_EVAL>(sh, P, x, O, st);
     if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_EVAL>(sh, P, x, O, st);
@@ -128,8 +130,8 @@ hipError_t rows_lsg(const EvalShape& sh, int P, const double* x, const OutView& 
 template <int L>
 hipError_t launch_rows(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st) {
 #define PE_X(L_, S_, G_) \
-  if constexpr (L == L_) \
-    if (sh.seg == S_ && sh.G == G_) return rows_lsg<L_, S_, G_>(sh, P, x, O, mode, st);
+  if constexpr (limbs_of(L) == L_) \
+    if (sh.seg == S_ && sh.G == G_) return rows_lsg<L, S_, G_>(sh, P, x, O, mode, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
@@ -144,7 +146,7 @@ hipError_t launch_adj_t(const EvalShape& sh, int P, const double* x, const doubl
   if (e != hipSuccess) return e;
   const int n = sh.view.n;
   hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * NG)), dim3(G * kSub), lds, st, sh.view, x,
-                     int64_t(2) * L * n, v, int64_t(2) * L * sh.view.N, NG, gsize, part);
+                     int64_t(width_of(L)) * n, v, int64_t(width_of(L)) * sh.view.N, NG, gsize, part);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = int64_t(P) * n;
@@ -181,10 +183,24 @@ hipError_t launch_adjoint(const EvalShape& sh, int P, const double* x, const dou
   const int G = sh.G == 2 ? 2 : 1;
 #define PE_X(L_, S_, G_) \
   if constexpr (L == L_ && G_ <= 2) \
-    if (sh.seg == S_ && G == G_) return adj_lsg<L_, S_, G_>(sh, P, x, v, NG, gsize, part, g, st);
+    if (sh.seg == S_ && G == G_) return adj_lsg<L, S_, G_>(sh, P, x, v, NG, gsize, part, g, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
+}
+
+// persistent grid: as many workgroups as fit on the device at once, at most
+// one per item
+template <typename Kern>
+hipError_t persistent_grid(Kern kern, int threads, size_t lds, int64_t nitems, int64_t& grid) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, threads, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, nitems));
+  return hipSuccess;
 }
 
 template <int L, int SEG, int CPL, int G, int MODE>
@@ -192,20 +208,49 @@ hipError_t launch_batch_t(const BatchShape& K, int P, const double* x, const Bat
   auto kern = batch_rows_kernel<L, SEG, CPL, G, MODE>;
   hipError_t e = allow_lds(kern, K.lds);
   if (e != hipSuccess) return e;
-  int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, G * kSub, K.lds);
-  if (e != hipSuccess) return e;
-  int dev = 0, cus = 0;
-  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(std::max(per_cu, 1)) * cus, K.nitems));
+  int64_t grid = 0;
+  if ((e = persistent_grid(kern, G * kSub, K.lds, K.nitems, grid)) != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(G * kSub), K.lds, st, K.views, K.items, K.nitems, K.counter,
                      P, x, K.x_off, out);
   return hipGetLastError();
 }
 
+template <int L, int SEG, int VW, int MODE>
+hipError_t launch_batch_small_t(const BatchShape& K, int P, const double* x, const BatchOut& out, hipStream_t st) {
+  auto kern = batch_small_kernel<L, SEG, VW, MODE>;
+  hipError_t e = allow_lds(kern, K.lds);
+  if (e != hipSuccess) return e;
+  int64_t grid = 0;
+  if ((e = persistent_grid(kern, kSub, K.lds, K.nitems, grid)) != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kSub), K.lds, st, K.views, K.items, K.nitems, K.counter, P, x,
+                     K.x_off, out);
+  return hipGetLastError();
+}
+
+template <int L, int SEG>
+hipError_t batch_small_ls(const BatchShape& K, int P, const double* x, const BatchOut& out, int mode,
+                          hipStream_t st) {
+  switch (K.vw * 4 + mode) {
+#define PE_CASE(VW, MODE) \
+  case VW * 4 + MODE:     \
+    return launch_batch_small_t<L, SEG, VW, MODE>(K, P, x, out, st);
+    PE_CASE(32, MODE_EVAL)
+    PE_CASE(32, MODE_FONLY)
+    PE_CASE(64, MODE_EVAL)
+    PE_CASE(64, MODE_FONLY)
+    PE_CASE(128, MODE_EVAL)
+    PE_CASE(128, MODE_FONLY)
+    PE_CASE(256, MODE_EVAL)
+    PE_CASE(256, MODE_FONLY)
+#undef PE_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int L, int SEG, int G>
 hipError_t batch_lsg(const BatchShape& K, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
+  if constexpr (G == 1)
+    if (K.vw > 0) return batch_small_ls<L, SEG>(K, P, x, out, mode, st);
   switch (K.cpl * 4 + mode) {
 #define PE_CASE(CPL, MODE) \
   case CPL * 4 + MODE:     \
@@ -228,7 +273,7 @@ hipError_t launch_batch(const BatchShape& K, int P, const double* x, const Batch
                         hipStream_t st) {
 #define PE_X(L_, S_, G_) \
   if constexpr (L == L_ && G_ <= 2) \
-    if (K.seg == S_ && K.G == G_) return batch_lsg<L_, S_, G_>(K, P, x, out, mode, st);
+    if (K.seg == S_ && K.G == G_) return batch_lsg<L, S_, G_>(K, P, x, out, mode, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;
@@ -242,7 +287,7 @@ hipError_t launch_mgs(int P, int N, int n, double* W, int64_t w_pt, double* R, i
   hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(unsigned(P)), dim3(kMgsThreads), lds, st, N, n, W, w_pt, R, r_pt, Y, y_pt, x,
-                     int64_t(2) * L * n, resid);
+                     int64_t(width_of(L)) * n, resid);
   return hipGetLastError();
 }
 
@@ -290,7 +335,7 @@ hipError_t ls_sweep(const LsView& V, int P, hipStream_t st) {
 template <int L>
 hipError_t ls_sweep_for(const LsView& V, int P, hipStream_t st) {
   const int N = V.N;
-  if constexpr (L <= 2) {
+  if constexpr (width_of(L) <= 4) {
     if (N <= 256) return ls_sweep<L, 256, 1>(V, P, st);
     if (N <= 512) return ls_sweep<L, 256, 2>(V, P, st);
     if (N <= 1024) return ls_sweep<L, 256, 4>(V, P, st);
@@ -313,7 +358,7 @@ hipError_t launch_lstsq(const LsLayout& lo, void* ws, const double* A, int64_t l
   const LsView V = ls_view(lo, ws);
   const int P = lo.P, N = lo.N, n = lo.n;
   const int tiles = ((n + 1 + 63) / 64) * ((N + 63) / 64);
-  hipLaunchKernelGGL(ls_copy_in_kernel<L>, dim3(unsigned(tiles), unsigned(2 * L), unsigned(P)), dim3(256), 0, st, V,
+  hipLaunchKernelGGL(ls_copy_in_kernel<L>, dim3(unsigned(tiles), unsigned(width_of(L)), unsigned(P)), dim3(256), 0, st, V,
                      A, ld, a_plane, a_pt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -44,6 +44,8 @@ struct ChunkDesc {
 // per-monomial metadata (packed order): the number of variables k
 inline uint32_t mon_meta(uint32_t k) { return k; }
 
+constexpr int kRealLevel = 8;  // flag of the level code for real numbers
+constexpr uint32_t kNoOcc = 0xffffffffu;  // input occurrence index of a neutral record
 constexpr int kRowDesc = 4;      // first chunk descriptors of each row, stored by row
 constexpr int kMaxVars = 65535;
 constexpr int kMaxSeg = 16;      // largest segment any kernel variant handles

@@ -34,6 +34,7 @@
 
 #include "eval_kernels.hpp"
 #include "mdarith.hpp"
+#include "newton_kernels.hpp"
 
 namespace pe {
 
@@ -62,11 +63,11 @@ inline LsLayout ls_layout(int L, int N, int n, int P) {
   lo.N = N;
   lo.n = n;
   lo.P = P;
-  lo.w_pt = int64_t(2) * L * (n + 1) * N;
-  lo.r_pt = int64_t(2) * L * (n + 1) * n;
-  lo.nrm_pt = int64_t(n + 1) * L;
+  lo.w_pt = int64_t(width_of(L)) * (n + 1) * N;
+  lo.r_pt = int64_t(width_of(L)) * (n + 1) * n;
+  lo.nrm_pt = int64_t(n + 1) * limbs_of(L);
   lo.rmax_pt = n + 1;
-  lo.y_pt = int64_t(2) * L * n;
+  lo.y_pt = int64_t(width_of(L)) * n;
   size_t off = 0;
   lo.w_off = off;
   off = ls_align256(off + size_t(P) * lo.w_pt * 8);
@@ -121,7 +122,7 @@ inline LsView ls_view(const LsLayout& lo, void* base) {
 
 template <int L>
 __host__ __device__ constexpr double ls_unit() {
-  return L == 1 ? 0x1p-53 : (L == 2 ? 0x1p-104 : 0x1p-206);
+  return limbs_of(L) == 1 ? 0x1p-53 : (limbs_of(L) == 2 ? 0x1p-104 : 0x1p-206);
 }
 
 // ------------------------------------------------------------------ copy in
@@ -176,11 +177,11 @@ __device__ __forceinline__ V wg_sum(V v, V* red, Add add, Shfl shfl) {
   return s;
 }
 
-template <int L>
-__device__ __forceinline__ R<L> shfl_xor_r(const R<L>& v, int mask) {
-  R<L> r;
+template <int NL>
+__device__ __forceinline__ R<NL> shfl_xor_r(const R<NL>& v, int mask) {
+  R<NL> r;
 #pragma unroll
-  for (int l = 0; l < L; ++l) r.x[l] = __shfl_xor(v.x[l], mask);
+  for (int l = 0; l < NL; ++l) r.x[l] = __shfl_xor(v.x[l], mask);
   return r;
 }
 
@@ -193,8 +194,10 @@ __device__ __forceinline__ R<L> shfl_xor_r(const R<L>& v, int mask) {
 // threshold below which a pivot counts as zero.
 template <int L, int T, int EPT>
 __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, int j0, int j1) {
+  using RL = R<limbs_of(L)>;
+  constexpr int NL = limbs_of(L);
   __shared__ C<L> red_c[T / 64];
-  __shared__ R<L> red_r[T / 64];
+  __shared__ RL red_r[T / 64];
   const int ncol = V.n + 1;
   const int cols = j1 - j0;
   const int p = blockIdx.x / cols;
@@ -213,14 +216,14 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
   const int cend = min(k1, j);
   auto cadd = [](const C<L>& x, const C<L>& y) { return c_add(x, y); };
   auto cshf = [](const C<L>& x, int m) { return shfl_xor_c(x, m); };
-  auto radd = [](const R<L>& x, const R<L>& y) { return r_add(x, y); };
-  auto rshf = [](const R<L>& x, int m) { return shfl_xor_r(x, m); };
+  auto radd = [](const RL& x, const RL& y) { return r_add(x, y); };
+  auto rshf = [](const RL& x, int m) { return shfl_xor_r(x, m); };
   const double thresh = double(V.n) * ls_unit<L>();
   for (int c = k0; c < cend; ++c) {
-    R<L> nc;
+    RL nc;
 #pragma unroll
-    for (int l = 0; l < L; ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * L + l];
-    const R<L> rcc = r_sqrt(nc);
+    for (int l = 0; l < NL; ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * NL + l];
+    const RL rcc = r_sqrt(nc);
     const double rmax = V.rmax[p * V.rmax_pt + c];
     if (!(rcc.x[0] > thresh * rmax)) {
       if (j == c + 1 && tid == 0) V.flag[p] = 1;
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
     // the pivot's rows: kept in registers for the update in double and
     // double double; quad double loads them again (an L2 hit) so that the
     // column alone fills the registers
-    constexpr bool kKeep = L <= 2;
+    constexpr bool kKeep = width_of(L) <= 4;
     C<L> q[kKeep ? EPT : 1];
     C<L> dot = c_zero<L>();
 #pragma unroll
@@ -240,18 +243,13 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
       dot = c_add(dot, c_mul(c_conj(qe), a[e]));
     }
     dot = wg_sum<T>(dot, red_c, cadd, cshf);
-    const R<L> inv_r = r_recip(rcc);
-    const R<L> inv_n = r_recip(nc);
+    const RL inv_r = r_recip(rcc);
+    const RL inv_n = r_recip(nc);
     double* Rp = V.R + p * V.r_pt;
     const int64_t rplane = int64_t(ncol) * V.n;
     if (tid == 0) {
       store_planar(Rp + int64_t(j) * V.n, rplane, c, c_mul_r(dot, inv_r));
-      if (j == c + 1) {
-        C<L> d;
-        d.re = rcc;
-        d.im = r_zero<L>();
-        store_planar(Rp + int64_t(c) * V.n, rplane, c, d);
-      }
+      if (j == c + 1) store_planar(Rp + int64_t(c) * V.n, rplane, c, c_from_r<L>(rcc));
     }
     const C<L> f = c_neg(c_mul_r(dot, inv_n));
 #pragma unroll
@@ -273,13 +271,13 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
     }
   }
   if (j == k1) {
-    R<L> s = r_zero<L>();
+    RL s = r_zero<NL>();
 #pragma unroll
     for (int e = 0; e < EPT; ++e) s = r_add(s, c_norm2(a[e]));
     s = wg_sum<T>(s, red_r, radd, rshf);
     if (tid == 0) {
 #pragma unroll
-      for (int l = 0; l < L; ++l) V.nrm[p * V.nrm_pt + int64_t(j) * L + l] = s.x[l];
+      for (int l = 0; l < NL; ++l) V.nrm[p * V.nrm_pt + int64_t(j) * NL + l] = s.x[l];
       const double r = r_sqrt(s).x[0];
       const double prev = j > 0 ? V.rmax[p * V.rmax_pt + j - 1] : 0.0;
       V.rmax[p * V.rmax_pt + j] = fmax(prev, r);
@@ -319,7 +317,7 @@ __global__ __launch_bounds__(kBs) void ls_backsub_diag_kernel(LsView V, int s, i
   __syncthreads();
   for (int j = e - 1; j >= s; --j) {
     if (tid == 0) {
-      const R<L> rjj = load_planar<L>(Rp + int64_t(j) * V.n, rplane, j).re;
+      const R<limbs_of(L)> rjj = load_planar<L>(Rp + int64_t(j) * V.n, rplane, j).re;
       xj = c_mul_r(ysh[j - s], r_recip(rjj));
       ysh[j - s] = xj;
     }
@@ -368,7 +366,7 @@ __global__ __launch_bounds__(256) void ls_finish_kernel(LsView V, double* __rest
     const C<L> d = singular ? c_zero<L>() : load_planar<L>(V.y + p * V.y_pt, V.n, j);
     double* xp = x + p * x_pt;
     store_planar(xp, V.n, j, add ? c_add(load_planar<L>(xp, V.n, j), d) : d);
-    dmax = fmax(dmax, fmax(fabs(d.re.x[0]), fabs(d.im.x[0])));
+    dmax = fmax(dmax, fmax(fabs(d.re.x[0]), fabs(im_lead(d))));
   }
   red[tid] = dmax;
   __syncthreads();
@@ -390,7 +388,7 @@ __global__ __launch_bounds__(256) void ls_bnorm_kernel(LsView V, double* __restr
   const double* b = V.W + p * V.w_pt + int64_t(V.n) * V.N;
   double s = 0.0;
   for (int i = tid; i < V.N; i += 256) {
-    const double re = b[i], im = b[int64_t(L) * plane + i];
+    const double re = b[i], im = is_real(L) ? 0.0 : b[int64_t(limbs_of(L)) * plane + i];
     s += re * re + im * im;
   }
   red[tid] = s;
@@ -415,16 +413,16 @@ __global__ void ls_export_kernel(LsView V, double* __restrict__ Rout, double* __
   if (Rout && idx < int64_t(V.n) * ncol) {
     const int i = int(idx / ncol), j = int(idx - int64_t(i) * ncol);
     const C<L> r = (i <= j) ? load_planar<L>(V.R + p * V.r_pt + int64_t(j) * V.n, rplane, i) : c_zero<L>();
-    store_planar(Rout + p * (int64_t(2) * L * rplane), rplane, idx, r);
+    store_planar(Rout + p * (int64_t(width_of(L)) * rplane), rplane, idx, r);
   }
   if (Qout && idx < int64_t(V.N) * V.n) {
     const int i = int(idx / V.n), c = int(idx - int64_t(i) * V.n);
-    R<L> nc;
+    R<limbs_of(L)> nc;
 #pragma unroll
-    for (int l = 0; l < L; ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * L + l];
+    for (int l = 0; l < limbs_of(L); ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * limbs_of(L) + l];
     const int64_t plane = int64_t(ncol) * V.N;
     const C<L> q = c_mul_r(load_planar<L>(V.W + p * V.w_pt + int64_t(c) * V.N, plane, i), r_recip(r_sqrt(nc)));
-    store_planar(Qout + p * (int64_t(2) * L * V.N * V.n), int64_t(V.N) * V.n, idx, q);
+    store_planar(Qout + p * (int64_t(width_of(L)) * V.N * V.n), int64_t(V.N) * V.n, idx, q);
   }
 }
 

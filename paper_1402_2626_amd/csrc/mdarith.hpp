@@ -273,66 +273,119 @@ PE_HD R<L> r_sqrt(const R<L>& a) {
   return r_add(s, r_mul_d(r_mul(z, d), 0.5));
 }
 
-// ------------------------------------------------------------------ complex level-L
+// ------------------------------------------------------------------ level codes
+//
+// A level code names the number type of a kernel instance: 1, 2, 4 are
+// complex numbers of L = 1, 2, 4 limbs per real part; 8 | L (9, 10, 12) are
+// real numbers of L limbs.  Real numbers use the same interface as complex
+// ones (C<code> with only a real part), so every kernel is written once.
+
+constexpr int kRealCode = 8;
+constexpr int limbs_of(int code) { return code & 7; }
+constexpr bool is_real(int code) { return (code & kRealCode) != 0; }
+// doubles per number
+constexpr int width_of(int code) { return is_real(code) ? limbs_of(code) : 2 * limbs_of(code); }
+
+// ------------------------------------------------------------------ complex (or real) level-L
+
+template <int L, bool REAL = is_real(L)>
+struct C;
 
 template <int L>
-struct C {
+struct C<L, false> {
   R<L> re, im;
 };
 
 template <int L>
+struct C<L, true> {
+  R<limbs_of(L)> re;
+};
+
+template <int L>
 PE_HD C<L> c_zero() {
-  return C<L>{r_zero<L>(), r_zero<L>()};
+  if constexpr (is_real(L))
+    return C<L>{r_zero<limbs_of(L)>()};
+  else
+    return C<L>{r_zero<L>(), r_zero<L>()};
 }
 
 template <int L>
 PE_HD C<L> c_one() {
-  return C<L>{r_from_double<L>(1.0), r_zero<L>()};
+  if constexpr (is_real(L))
+    return C<L>{r_from_double<limbs_of(L)>(1.0)};
+  else
+    return C<L>{r_from_double<L>(1.0), r_zero<L>()};
 }
 
 template <int L>
 PE_HD C<L> c_conj(const C<L>& a) {
-  return C<L>{a.re, r_neg(a.im)};
+  if constexpr (is_real(L))
+    return a;
+  else
+    return C<L>{a.re, r_neg(a.im)};
 }
 
 template <int L>
 PE_HD C<L> c_neg(const C<L>& a) {
-  return C<L>{r_neg(a.re), r_neg(a.im)};
+  if constexpr (is_real(L))
+    return C<L>{r_neg(a.re)};
+  else
+    return C<L>{r_neg(a.re), r_neg(a.im)};
 }
 
 template <int L>
 PE_HD C<L> c_add(const C<L>& a, const C<L>& b) {
-  return C<L>{r_add(a.re, b.re), r_add(a.im, b.im)};
+  if constexpr (is_real(L))
+    return C<L>{r_add(a.re, b.re)};
+  else
+    return C<L>{r_add(a.re, b.re), r_add(a.im, b.im)};
 }
 
 template <int L>
 PE_HD C<L> c_sub(const C<L>& a, const C<L>& b) {
-  return C<L>{r_sub(a.re, b.re), r_sub(a.im, b.im)};
+  if constexpr (is_real(L))
+    return C<L>{r_sub(a.re, b.re)};
+  else
+    return C<L>{r_sub(a.re, b.re), r_sub(a.im, b.im)};
 }
 
 // product by a real double (small integer exponents, real scalings)
 template <int L>
 PE_HD C<L> c_mul_d(const C<L>& a, double d) {
-  return C<L>{r_mul_d(a.re, d), r_mul_d(a.im, d)};
+  if constexpr (is_real(L))
+    return C<L>{r_mul_d(a.re, d)};
+  else
+    return C<L>{r_mul_d(a.re, d), r_mul_d(a.im, d)};
 }
 
 template <int L>
-PE_HD C<L> c_mul_r(const C<L>& a, const R<L>& d) {
-  return C<L>{r_mul(a.re, d), r_mul(a.im, d)};
+PE_HD C<L> c_mul_r(const C<L>& a, const R<limbs_of(L)>& d) {
+  if constexpr (is_real(L))
+    return C<L>{r_mul(a.re, d)};
+  else
+    return C<L>{r_mul(a.re, d), r_mul(a.im, d)};
 }
 
 // |a|^2 as a real level-L number
 template <int L>
-PE_HD R<L> c_norm2(const C<L>& a) {
-  return r_add(r_mul(a.re, a.re), r_mul(a.im, a.im));
+PE_HD R<limbs_of(L)> c_norm2(const C<L>& a) {
+  if constexpr (is_real(L))
+    return r_mul(a.re, a.re);
+  else
+    return r_add(r_mul(a.re, a.re), r_mul(a.im, a.im));
 }
 
-// generic complex product: four real products, two real additions
+// generic product: for complex numbers four real products and two real
+// additions; for real numbers the real product
 template <int L>
 PE_HD C<L> c_mul(const C<L>& a, const C<L>& b) {
-  R<L> ac = r_mul(a.re, b.re), bd = r_mul(a.im, b.im);
-  R<L> ad = r_mul(a.re, b.im), bc = r_mul(a.im, b.re);
-  return C<L>{r_sub(ac, bd), r_add(ad, bc)};
+  if constexpr (is_real(L)) {
+    return C<L>{r_mul(a.re, b.re)};
+  } else {
+    R<L> ac = r_mul(a.re, b.re), bd = r_mul(a.im, b.im);
+    R<L> ad = r_mul(a.re, b.im), bc = r_mul(a.im, b.re);
+    return C<L>{r_sub(ac, bd), r_add(ad, bc)};
+  }
 }
 
 // L = 1: contraction written explicitly

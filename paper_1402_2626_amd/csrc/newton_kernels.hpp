@@ -38,6 +38,29 @@ __device__ __forceinline__ C<L> c_mul_conj_a(const C<L>& a, const C<L>& b) {
   return c_mul(c_conj(a), b);
 }
 
+// leading limb of the imaginary part (0 for a real number)
+template <int L>
+__device__ __forceinline__ double im_lead(const C<L>& a) {
+  if constexpr (is_real(L))
+    return 0.0;
+  else
+    return a.im.x[0];
+}
+
+// a real level-L number as a complex (or real) one
+template <int L>
+__device__ __forceinline__ C<L> c_from_r(const R<limbs_of(L)>& r) {
+  C<L> d = c_zero<L>();
+  d.re = r;
+  return d;
+}
+
+// unit roundoff of the level: 2^-53, 2^-104, 2^-206 for 1, 2, 4 limbs
+template <int L>
+__host__ __device__ constexpr double level_unit() {
+  return limbs_of(L) == 1 ? 0x1p-53 : (limbs_of(L) == 2 ? 0x1p-104 : 0x1p-206);
+}
+
 // Per point: A (planar [2][L][N][ld], ld = n + 1, column n = b) is
 // overwritten; Rw gets R as [n][n+1] complex AoS (diagonal real); yw is
 // [n] complex AoS scratch for the back substitution; x is updated.
@@ -45,19 +68,21 @@ template <int L, int T>
 __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __restrict__ Rm,
                                 double* __restrict__ Y, double* __restrict__ xp, double* __restrict__ res2,
                                 double* lds) {
+  using RL = R<limbs_of(L)>;
+  constexpr int W = width_of(L);
   const int tid = threadIdx.x;
   const int ld = n + 1;
   const int64_t plane = int64_t(N) * ld;
-  double* colk = lds;                             // N complex, AoS
-  double* sh = colk + size_t(N) * 2 * L;          // [0..L): |a_k|^2 of the next pivot
-  double* red = sh + 2 * L;                       // T doubles for reductions
+  double* colk = lds;                             // N numbers, AoS
+  double* sh = colk + size_t(N) * W;              // |a_k|^2 of the next pivot
+  double* red = sh + W;                           // T doubles for reductions
   int* flag = reinterpret_cast<int*>(red + T);    // singular flag
 
   // |F|_2 from the leading limbs of b = -F
   double fs = 0.0;
   for (int i = tid; i < N; i += T) {
     const double re = A[0 * plane + int64_t(i) * ld + n];
-    const double im = A[int64_t(L) * plane + int64_t(i) * ld + n];
+    const double im = is_real(L) ? 0.0 : A[int64_t(limbs_of(L)) * plane + int64_t(i) * ld + n];
     fs += re * re + im * im;
   }
   red[tid] = fs;
@@ -72,43 +97,38 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
 
   // squared norm of column 0
   if (tid == 0) {
-    R<L> s2 = r_zero<L>();
+    RL s2 = r_zero<limbs_of(L)>();
     for (int i = 0; i < N; ++i) s2 = r_add(s2, c_norm2(load_planar<L>(A, plane, int64_t(i) * ld)));
     r_store_aos(sh, s2);
   }
   double rmax = 0.0;
-  const double uL = (L == 1) ? 0x1p-53 : (L == 2 ? 0x1p-104 : 0x1p-206);
+  const double uL = level_unit<L>();
 
   for (int k = 0; k < n; ++k) {
-    for (int i = tid; i < N; i += T) store_aos(colk + size_t(i) * 2 * L, load_planar<L>(A, plane, int64_t(i) * ld + k));
+    for (int i = tid; i < N; i += T) store_aos(colk + size_t(i) * W, load_planar<L>(A, plane, int64_t(i) * ld + k));
     __syncthreads();
-    const R<L> nk = r_load_aos<L>(sh);
-    const R<L> rkk = r_sqrt(nk);
+    const RL nk = r_load_aos<limbs_of(L)>(sh);
+    const RL rkk = r_sqrt(nk);
     rmax = fmax(rmax, rkk.x[0]);
     if (!(rkk.x[0] > double(n) * uL * rmax)) {
       if (tid == 0) *flag = 1;
       break;  // uniform: every thread reads the same values
     }
-    const R<L> inv_n = r_recip(nk);
-    const R<L> inv_r = r_recip(rkk);
-    if (tid == 0) {
-      C<L> d;
-      d.re = rkk;
-      d.im = r_zero<L>();
-      store_aos(Rm + (size_t(k) * ld + k) * 2 * L, d);
-    }
+    const RL inv_n = r_recip(nk);
+    const RL inv_r = r_recip(rkk);
+    if (tid == 0) store_aos(Rm + (size_t(k) * ld + k) * W, c_from_r<L>(rkk));
     __syncthreads();  // everyone has read sh before it is overwritten below
     for (int j = k + 1 + tid; j <= n; j += T) {
       C<L> dot = c_zero<L>();
       for (int i = 0; i < N; ++i)
-        dot = c_add(dot, c_mul_conj_a(load_aos<L>(colk + size_t(i) * 2 * L), load_planar<L>(A, plane, int64_t(i) * ld + j)));
-      store_aos(Rm + (size_t(k) * ld + j) * 2 * L, c_mul_r(dot, inv_r));
+        dot = c_add(dot, c_mul_conj_a(load_aos<L>(colk + size_t(i) * W), load_planar<L>(A, plane, int64_t(i) * ld + j)));
+      store_aos(Rm + (size_t(k) * ld + j) * W, c_mul_r(dot, inv_r));
       const C<L> cr = c_neg(c_mul_r(dot, inv_n));
       const bool next = (j == k + 1);
-      R<L> s2 = r_zero<L>();
+      RL s2 = r_zero<limbs_of(L)>();
       for (int i = 0; i < N; ++i) {
         C<L> a = load_planar<L>(A, plane, int64_t(i) * ld + j);
-        a = c_add(a, c_mul(cr, load_aos<L>(colk + size_t(i) * 2 * L)));
+        a = c_add(a, c_mul(cr, load_aos<L>(colk + size_t(i) * W)));
         store_planar(A, plane, int64_t(i) * ld + j, a);
         if (next) s2 = r_add(s2, c_norm2(a));
       }
@@ -121,18 +141,18 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
 
   // back substitution R dx = y, y = column n of R; dx overwrites Y
   if (!singular) {
-    for (int i = tid; i < n; i += T) store_aos(Y + size_t(i) * 2 * L, load_aos<L>(Rm + (size_t(i) * ld + n) * 2 * L));
+    for (int i = tid; i < n; i += T) store_aos(Y + size_t(i) * W, load_aos<L>(Rm + (size_t(i) * ld + n) * W));
     __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
       if (tid == 0) {
-        const R<L> rkk = load_aos<L>(Rm + (size_t(k) * ld + k) * 2 * L).re;
-        store_aos(Y + size_t(k) * 2 * L, c_mul_r(load_aos<L>(Y + size_t(k) * 2 * L), r_recip(rkk)));
+        const RL rkk = load_aos<L>(Rm + (size_t(k) * ld + k) * W).re;
+        store_aos(Y + size_t(k) * W, c_mul_r(load_aos<L>(Y + size_t(k) * W), r_recip(rkk)));
       }
       __syncthreads();
-      const C<L> dk = load_aos<L>(Y + size_t(k) * 2 * L);
+      const C<L> dk = load_aos<L>(Y + size_t(k) * W);
       for (int i = tid; i < k; i += T) {
-        const C<L> t = c_mul(load_aos<L>(Rm + (size_t(i) * ld + k) * 2 * L), dk);
-        store_aos(Y + size_t(i) * 2 * L, c_sub(load_aos<L>(Y + size_t(i) * 2 * L), t));
+        const C<L> t = c_mul(load_aos<L>(Rm + (size_t(i) * ld + k) * W), dk);
+        store_aos(Y + size_t(i) * W, c_sub(load_aos<L>(Y + size_t(i) * W), t));
       }
       __syncthreads();
     }
@@ -141,9 +161,9 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
   double dmax = 0.0;
   for (int j = tid; j < n; j += T) {
     if (!singular) {
-      const C<L> d = load_aos<L>(Y + size_t(j) * 2 * L);
+      const C<L> d = load_aos<L>(Y + size_t(j) * W);
       store_planar(xp, n, j, c_add(load_planar<L>(xp, n, j), d));
-      dmax = fmax(dmax, fmax(fabs(d.re.x[0]), fabs(d.im.x[0])));
+      dmax = fmax(dmax, fmax(fabs(d.re.x[0]), fabs(im_lead(d))));
     }
   }
   red[tid] = dmax;
@@ -189,10 +209,10 @@ __global__ __launch_bounds__(T) void mgs_solve_batch_kernel(const BatchNewtonDes
   const int s = order[blockIdx.x / P];
   const int pt = blockIdx.x - (blockIdx.x / P) * P;
   const BatchNewtonDesc d = desc[s];
-  const int64_t w_pt = int64_t(2) * L * d.N * (d.n + 1);
-  const int64_t r_pt = int64_t(d.n) * (d.n + 1) * 2 * L;
-  const int64_t y_pt = int64_t(d.n) * 2 * L;
-  const int64_t x_pt = int64_t(2) * L * d.n;
+  const int64_t w_pt = int64_t(width_of(L)) * d.N * (d.n + 1);
+  const int64_t r_pt = int64_t(d.n) * (d.n + 1) * width_of(L);
+  const int64_t y_pt = int64_t(d.n) * width_of(L);
+  const int64_t x_pt = int64_t(width_of(L)) * d.n;
   mgs_solve_point<L, T>(d.N, d.n, W + d.w_off * P + pt * w_pt, Rw + d.r_off * P + pt * r_pt,
                         yw + d.y_off * P + pt * y_pt, X + d.x_off * P + pt * x_pt,
                         resid ? resid + (int64_t(s) * P + pt) * 2 : nullptr, lds);
@@ -203,7 +223,7 @@ __global__ __launch_bounds__(T) void mgs_solve_batch_kernel(const BatchNewtonDes
 // b = -f(x) into column n of the augmented matrices (row-major planar, point
 // stride w_pt, plane stride plane, row stride ld); this replaces it by
 // wF b + wc c_p with wF in {0, 1}: (1, t) is the corrector at t, (0, dt) the
-// Euler predictor J dx = c dt.  c is [P][2L][N]; grid over P * N.
+// Euler predictor J dx = c dt.  c is [P][components][N]; grid over P * N.
 template <int L>
 __global__ void rhs_shift_kernel(double* __restrict__ W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P,
                                  const double* __restrict__ c, double wF, double wc) {
@@ -211,13 +231,13 @@ __global__ void rhs_shift_kernel(double* __restrict__ W, int64_t w_pt, int64_t p
   if (idx >= int64_t(P) * N) return;
   const int p = int(idx / N), i = int(idx - int64_t(p) * N);
   double* b = W + p * w_pt + int64_t(i) * ld + n;
-  const C<L> sc = c_mul_d(load_planar<L>(c + int64_t(p) * 2 * L * N, N, i), wc);
+  const C<L> sc = c_mul_d(load_planar<L>(c + int64_t(p) * width_of(L) * N, N, i), wc);
   store_planar(b, plane, 0, wF == 0.0 ? sc : c_add(load_planar<L>(b, plane, 0), sc));
 }
 
 template <int L>
 __host__ __device__ inline size_t mgs_lds_bytes(int N) {
-  return size_t(N) * 2 * L * sizeof(double) + 2 * L * sizeof(double) + kMgsThreads * sizeof(double) + 16;
+  return size_t(N) * width_of(L) * sizeof(double) + width_of(L) * sizeof(double) + kMgsThreads * sizeof(double) + 16;
 }
 
 }  // namespace pe

@@ -20,8 +20,9 @@ int lanes_for(int k, int seg) {
 }
 
 int validate(const SysInput& in, std::string& msg) {
-  if (in.level != 1 && in.level != 2 && in.level != 4) {
-    msg = "level must be 1, 2 or 4";
+  // level codes: 1, 2, 4 complex; 8 | 1, 8 | 2, 8 | 4 real (layout.hpp)
+  if ((in.level & ~kRealLevel) != 1 && (in.level & ~kRealLevel) != 2 && (in.level & ~kRealLevel) != 4) {
+    msg = "level must be 1, 2 or 4, optionally with the real flag 8";
     return kEinval;
   }
   if (in.n_vars < 1) {
@@ -107,6 +108,7 @@ namespace {
 
 struct Occ {
   int var, exp;
+  int64_t orig;  // index of the occurrence in the input
 };
 
 }  // namespace
@@ -114,7 +116,9 @@ struct Occ {
 int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::string& msg) {
   int st = validate(in, msg);
   if (st != kOk) return st;
-  const int L = in.level, n = in.n_vars, N = in.n_polys;
+  const int L = in.level & ~kRealLevel, n = in.n_vars, N = in.n_polys;
+  const int ncomp = (in.level & kRealLevel) ? 1 : 2;  // real or complex
+  const int W = ncomp * L;                             // doubles per number
   const int64_t M = in.poly_ptr[N];
   const int64_t nnz = M > 0 ? in.mon_ptr[M] : 0;
   const int T = pp.threads, seg = pp.seg;
@@ -125,6 +129,7 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
 
   out = Packed();
   out.level = L;
+  out.code = in.level;
   out.n = n;
   out.N = N;
   out.M = M;
@@ -147,8 +152,9 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
     return kEinval;
   }
 
-  out.mcoef.resize(size_t(M) * 2 * L);
+  out.mcoef.resize(size_t(M) * W);
   out.mmeta.resize(size_t(M));
+  out.mon_orig.resize(size_t(M));
   out.chunk_ptr.assign(size_t(N) + 1, 0);
   out.poly_cost.assign(size_t(N), 0);
 
@@ -213,7 +219,7 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
         const int64_t t = order[i + g];
         const int64_t a = in.mon_ptr[t], b = in.mon_ptr[t + 1];
         occ_sorted.clear();
-        for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o]});
+        for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o], o});
         std::sort(occ_sorted.begin(), occ_sorted.end(), [](const Occ& x, const Occ& y) { return x.var < y.var; });
         for (int r = 0; r < int(occ_sorted.size()); ++r) contribs.push_back({occ_sorted[r].var, g, r});
         slot_of[size_t(g)].assign(occ_sorted.size(), 0);
@@ -239,13 +245,14 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
       const size_t rec0 = out.occ.size();
       const OccRec pad{uint16_t(n), 1, uint16_t(slots), 0};
       out.occ.resize(rec0 + size_t(segc) * cd.width, pad);
+      out.occ_orig.resize(rec0 + size_t(segc) * cd.width, kNoOcc);
       int64_t cost = 0;
       for (int g = 0; g < count; ++g) {
         const int64_t t = order[i + g];
         const int64_t a = in.mon_ptr[t], b = in.mon_ptr[t + 1];
         const int k = int(b - a);
         occ_sorted.clear();
-        for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o]});
+        for (int64_t o = a; o < b; ++o) occ_sorted.push_back({in.var_idx[o], in.exps[o], o});
         std::sort(occ_sorted.begin(), occ_sorted.end(), [](const Occ& x, const Occ& y) { return x.var < y.var; });
         // lane q of the group takes occurrences q, q + s, q + 2s, ... (in
         // variable order): a wavefront's gathers and slot stores at one step
@@ -262,13 +269,15 @@ int pack_system(const SysInput& in, const PackParams& pp, Packed& out, std::stri
             rec.var = uint16_t(oc.var);
             rec.exp = uint16_t(oc.exp);
             rec.slot = uint16_t(slot_of[size_t(g)][size_t(r)]);
+            out.occ_orig[rec0 + size_t(ii) * cd.width + size_t(lane)] = uint32_t(oc.orig);
           }
         }
         // packed monomial: coefficient and metadata
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < ncomp; ++c)
           for (int l = 0; l < L; ++l)
-            out.mcoef[size_t(packed_t + g) * 2 * L + size_t(c) * L + l] = in.coef[(size_t(c) * L + l) * size_t(M) + size_t(t)];
+            out.mcoef[size_t(packed_t + g) * W + size_t(c) * L + l] = in.coef[(size_t(c) * L + l) * size_t(M) + size_t(t)];
         out.mmeta[size_t(packed_t + g)] = mon_meta(uint32_t(k));
+        out.mon_orig[size_t(packed_t + g)] = uint32_t(t);
         cost += k;
       }
       out.poly_cost[p] += int64_t(segc) * s * count + cost;

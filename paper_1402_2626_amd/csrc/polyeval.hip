@@ -20,6 +20,8 @@
 
 using namespace pe;
 
+static_assert(PE_REAL == kRealCode && PE_REAL == kRealLevel, "one real flag for the ABI, the kernels and the packer");
+
 // ------------------------------------------------------------------ errors
 
 namespace {
@@ -117,7 +119,8 @@ struct Plan {
 
 struct pe_system {
   int device = 0;
-  int level = 0;
+  int level = 0;  // limbs per real part (1, 2, 4)
+  int code = 0;   // level code: level, plus PE_REAL for real arithmetic
   int n_vars = 0;
   // the input as given (host copy), for repacking with another launch shape
   std::vector<int64_t> in_poly_ptr, in_mon_ptr;
@@ -135,6 +138,10 @@ struct pe_system {
   mutable std::mutex ws_mu;
   mutable void* adj_ws = nullptr;
   mutable size_t adj_ws_bytes = 0;
+  // input-order maps of the packed records and monomials (uploaded by the
+  // first pe_eval_terms; freed with the packed arrays)
+  mutable uint32_t* d_occ_orig = nullptr;
+  mutable uint32_t* d_mon_orig = nullptr;
 };
 
 // ------------------------------------------------------------------ kernel dispatch
@@ -155,10 +162,13 @@ EvalShape eval_shape(const pe_system* sys) {
 hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const OutView& O, int mode,
                          hipStream_t st) {
   const EvalShape sh = eval_shape(sys);
-  switch (sys->level) {
+  switch (sys->code) {
     case 1: return launch_rows<1>(sh, P, x, O, mode, st);
     case 2: return launch_rows<2>(sh, P, x, O, mode, st);
     case 4: return launch_rows<4>(sh, P, x, O, mode, st);
+    case PE_REAL | 1: return launch_rows<PE_REAL | 1>(sh, P, x, O, mode, st);
+    case PE_REAL | 2: return launch_rows<PE_REAL | 2>(sh, P, x, O, mode, st);
+    case PE_REAL | 4: return launch_rows<PE_REAL | 4>(sh, P, x, O, mode, st);
   }
   return hipErrorInvalidValue;
 }
@@ -166,7 +176,7 @@ hipError_t dispatch_rows(const pe_system* sys, int P, const double* x, const Out
 hipError_t dispatch_adj(const pe_system* sys, int P, const double* x, const double* v, int NG, int gsize,
                         double* part, double* g, hipStream_t st) {
   const EvalShape sh = eval_shape(sys);
-  switch (sys->level) {
+  switch (sys->code) {
     case 1: return launch_adjoint<1>(sh, P, x, v, NG, gsize, part, g, st);
     case 2: return launch_adjoint<2>(sh, P, x, v, NG, gsize, part, g, st);
     case 4: return launch_adjoint<4>(sh, P, x, v, NG, gsize, part, g, st);
@@ -202,7 +212,9 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 variables is not supported");
   const size_t limit = device_lds_limit();
   const int L = H.level;
-  auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, G) * L; };
+  // lds_bytes<1> counts 2 doubles per number; the level's width is W
+  const int W = width_of(H.code);
+  auto lds_for = [&](int tf, int tl, int G) { return lds_bytes<1>(H.n, tf, tl, pl.max_slots, G) / 2 * W; };
   // table of powers in LDS, in order of preference: for D and DD x itself
   // first (its gathers are frequent next to cheap arithmetic) and then as
   // many powers as fit; for QD only powers >= 2.  In double precision, when
@@ -263,12 +275,15 @@ void free_device(pe_system* sys) {
   for (void* p : sys->allocs) (void)hipFree(p);
   sys->allocs.clear();
   sys->device_bytes = 0;
+  for (uint32_t* p : {sys->d_occ_orig, sys->d_mon_orig})
+    if (p) (void)hipFree(p);
+  sys->d_occ_orig = sys->d_mon_orig = nullptr;
 }
 
-// (Re)pack the stored input for segment length `seg`, choose G and upload.
-pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) {
+// the stored input as the packer takes it
+SysInput stored_input(const pe_system* sys) {
   SysInput in;
-  in.level = sys->level;
+  in.level = sys->code;
   in.n_vars = sys->n_vars;
   in.n_polys = int(sys->in_poly_ptr.size()) - 1;
   in.poly_ptr = sys->in_poly_ptr.data();
@@ -276,6 +291,12 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   in.var_idx = sys->in_var.data();
   in.exps = sys->in_exp.data();
   in.coef = sys->in_coef.data();
+  return in;
+}
+
+// (Re)pack the stored input for segment length `seg`, choose G and upload.
+pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) {
+  const SysInput in = stored_input(sys);
   PackParams pp;
   pp.threads = kSub;
   pp.seg = seg;
@@ -335,6 +356,10 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   sys->host.mcoef.shrink_to_fit();
   sys->host.colptr.clear();
   sys->host.colptr.shrink_to_fit();
+  sys->host.occ_orig.clear();
+  sys->host.occ_orig.shrink_to_fit();
+  sys->host.mon_orig.clear();
+  sys->host.mon_orig.shrink_to_fit();
   return PE_OK;
 }
 
@@ -346,7 +371,7 @@ std::string g_cache_path;
 std::string plan_key(const pe_system* sys) {
   const Packed& H = sys->host;
   std::ostringstream k;
-  k << "L" << sys->level << " n" << H.n << " N" << H.N << " M" << H.M << " nnz" << H.nnz << " kmax" << H.kmax
+  k << "L" << sys->code << " n" << H.n << " N" << H.N << " M" << H.M << " nnz" << H.nnz << " kmax" << H.kmax
     << " emax" << H.emax;
   return k.str();
 }
@@ -379,6 +404,16 @@ void cache_store(const std::string& key, int seg, int G, double us) {
   f << key << " | " << seg << " " << G << " " << us << "\n";
 }
 
+// Groups of polynomials of the adjoint: gsize consecutive polynomials per
+// workgroup, NG groups per point, enough workgroups (about 4096) to fill the
+// device.
+void adjoint_groups(int N, int P, int& NG, int& gsize) {
+  const int target = 4096;
+  gsize = int(std::max<int64_t>(1, (int64_t(N) * P + target - 1) / target));
+  gsize = std::min(gsize, N);
+  NG = (N + gsize - 1) / gsize;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -409,7 +444,8 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
   if (st != kOk) return fail(st, msg);
   auto* sys = new (std::nothrow) pe_system();
   if (!sys) return fail(PE_ENOMEM, "host allocation failed");
-  sys->level = level;
+  sys->level = level & ~PE_REAL;
+  sys->code = level;
   sys->n_vars = n_vars;
   const int64_t M = poly_ptr[n_polys];
   const int64_t nnz = M > 0 ? mon_ptr[M] : 0;
@@ -419,7 +455,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
     else sys->in_mon_ptr.assign(1, 0);
     sys->in_var.assign(var_idx, var_idx + nnz);
     sys->in_exp.assign(exps, exps + nnz);
-    sys->in_coef.assign(coef, coef + size_t(M) * 2 * level);
+    sys->in_coef.assign(coef, coef + size_t(M) * width_of(level));
   } catch (...) {
     delete sys;
     return fail(PE_ENOMEM, "host allocation failed");
@@ -430,7 +466,7 @@ pe_status pe_system_create(pe_system** out, int32_t level, int32_t n_vars, int32
     return fail(PE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
   }
   // launch shape: from the plan cache if it knows this system, else the default
-  int seg = default_seg_for(level, sys->in_mon_ptr), G = 0;
+  int seg = default_seg_for(sys->level, sys->in_mon_ptr), G = 0;
   pe_status ps = pack_and_upload(sys, seg, G, static_cast<hipStream_t>(stream));
   if (ps == PE_OK) {
     int cseg = 0, cG = 0;
@@ -460,7 +496,7 @@ pe_status pe_system_destroy(pe_system* sys) {
 pe_status pe_system_info(const pe_system* sys, int64_t info[11]) {
   if (!sys || !info) return fail(PE_EINVAL, "NULL argument");
   const Packed& H = sys->host;
-  info[0] = sys->level;
+  info[0] = sys->code;
   info[1] = H.n;
   info[2] = H.N;
   info[3] = H.M;
@@ -512,19 +548,85 @@ pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, d
   if (P == 0 || sys->view.N == 0) return PE_OK;
   if (!x || !F) return fail(PE_EINVAL, "x or F is NULL");
   if (int64_t(P) * sys->view.N > 0x7fffffffLL) return fail(PE_EUNSUPPORTED, "P * N too large");
-  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  const int W = width_of(sys->code), n = sys->view.n, N = sys->view.N;
   OutView O;
   O.J = J;
   O.j_plane = int64_t(N) * n;
-  O.j_pt = 2 * L * O.j_plane;
+  O.j_pt = W * O.j_plane;
   O.j_row = n;
   O.F = F;
   O.f_plane = N;
-  O.f_pt = 2 * L * int64_t(N);
+  O.f_pt = W * int64_t(N);
   O.f_row = 1;
   O.f_sign = 1.0;
   hipError_t e = dispatch_rows(sys, P, x, O, J ? MODE_EVAL : MODE_FONLY, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+pe_status pe_eval_terms(const pe_system* sys, int32_t P, const double* x, double* V, double* G, void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  const Packed& H = sys->host;
+  if (P == 0 || H.M == 0) return PE_OK;
+  if (!x || !V || (!G && H.nnz > 0)) return fail(PE_EINVAL, "x, V or G is NULL");
+  if (int64_t(P) * sys->view.N > 0x7fffffffLL) return fail(PE_EUNSUPPORTED, "P * N too large");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  {
+    // the input-order maps: the packing is deterministic, so packing the
+    // stored input again with the system's parameters gives the records'
+    // order on the device
+    std::lock_guard<std::mutex> lk(sys->ws_mu);
+    if (!sys->d_mon_orig) {
+      Packed R;
+      std::string msg;
+      const int st = pack_system(stored_input(sys), H.params, R, msg);
+      if (st != kOk) return fail(st, msg);
+      if (R.occ.size() != R.occ_orig.size() || R.chunks.size() != H.chunks.size())
+        return fail(PE_EDEVICE, "repacking for the input order did not reproduce the packing");
+      uint32_t *occ = nullptr, *mon = nullptr;
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&mon), R.mon_orig.size() * sizeof(uint32_t));
+      if (e == hipSuccess && !R.occ_orig.empty())
+        e = hipMalloc(reinterpret_cast<void**>(&occ), R.occ_orig.size() * sizeof(uint32_t));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(mon, R.mon_orig.data(), R.mon_orig.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs);
+      if (e == hipSuccess && occ)
+        e = hipMemcpyAsync(occ, R.occ_orig.data(), R.occ_orig.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs);
+      if (e == hipSuccess) e = hipStreamSynchronize(hs);
+      if (e != hipSuccess) {
+        if (mon) (void)hipFree(mon);
+        if (occ) (void)hipFree(occ);
+        return fail(e == hipErrorOutOfMemory ? PE_ENOMEM : PE_EDEVICE,
+                    std::string("input-order maps: ") + hipGetErrorString(e));
+      }
+      sys->d_occ_orig = occ;
+      sys->d_mon_orig = mon;
+    }
+  }
+  const int W = width_of(sys->code);
+  EvalShape sh = eval_shape(sys);
+  sh.view.occ_orig = sys->d_occ_orig;
+  sh.view.mon_orig = sys->d_mon_orig;
+  OutView O;
+  O.F = V;
+  O.f_plane = H.M;
+  O.f_pt = W * H.M;
+  O.f_row = 0;
+  O.f_sign = 1.0;
+  O.J = G;
+  O.j_plane = H.nnz;
+  O.j_pt = W * H.nnz;
+  O.j_row = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (sys->code) {
+    case 1: e = launch_rows<1>(sh, P, x, O, MODE_TERMS, hs); break;
+    case 2: e = launch_rows<2>(sh, P, x, O, MODE_TERMS, hs); break;
+    case 4: e = launch_rows<4>(sh, P, x, O, MODE_TERMS, hs); break;
+    case PE_REAL | 1: e = launch_rows<PE_REAL | 1>(sh, P, x, O, MODE_TERMS, hs); break;
+    case PE_REAL | 2: e = launch_rows<PE_REAL | 2>(sh, P, x, O, MODE_TERMS, hs); break;
+    case PE_REAL | 4: e = launch_rows<PE_REAL | 4>(sh, P, x, O, MODE_TERMS, hs); break;
+  }
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("terms launch: ") + hipGetErrorString(e));
   return PE_OK;
 }
 
@@ -534,17 +636,15 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
   if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
   if (P == 0) return PE_OK;
   if (!x || !v || !g) return fail(PE_EINVAL, "x, v or g is NULL");
+  if (is_real(sys->code)) return fail(PE_EUNSUPPORTED, "the adjoint is implemented for complex systems");
   const int L = sys->level, n = sys->view.n, N = sys->view.N;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (N == 0) {
     PE_HIP(hipMemsetAsync(g, 0, size_t(P) * 2 * L * n * sizeof(double), hs));
     return PE_OK;
   }
-  // groups of polynomials: enough workgroups to fill the device
-  const int target = 4096;
-  int gsize = int(std::max<int64_t>(1, (int64_t(N) * P + target - 1) / target));
-  gsize = std::min(gsize, N);
-  const int NG = (N + gsize - 1) / gsize;
+  int NG = 0, gsize = 0;
+  adjoint_groups(N, P, NG, gsize);
   const size_t need = size_t(P) * NG * 2 * L * n * sizeof(double);
   double* part = nullptr;
   {
@@ -579,11 +679,12 @@ struct NewtonLayout {
   int64_t w_pt, r_pt, y_pt;  // in doubles
 };
 
-NewtonLayout newton_layout(int L, int N, int n, int P) {
+// W: doubles per number of the level
+NewtonLayout newton_layout(int W, int N, int n, int P) {
   NewtonLayout lo;
-  lo.w_pt = int64_t(2) * L * N * (n + 1);
-  lo.r_pt = int64_t(n) * (n + 1) * 2 * L;
-  lo.y_pt = int64_t(n) * 2 * L;
+  lo.w_pt = int64_t(W) * N * (n + 1);
+  lo.r_pt = int64_t(n) * (n + 1) * W;
+  lo.y_pt = int64_t(n) * W;
   lo.w_off = 0;
   lo.r_off = align256(lo.w_off + size_t(P) * lo.w_pt * sizeof(double));
   lo.y_off = align256(lo.r_off + size_t(P) * lo.r_pt * sizeof(double));
@@ -591,16 +692,29 @@ NewtonLayout newton_layout(int L, int N, int n, int P) {
   return lo;
 }
 
-hipError_t dispatch_mgs(int L, int P, int N, int n, double* W, const NewtonLayout& lo, char* base, double* x,
+hipError_t dispatch_mgs(int code, int P, int N, int n, double* W, const NewtonLayout& lo, char* base, double* x,
                         double* resid, hipStream_t st) {
   double* R = reinterpret_cast<double*>(base + lo.r_off);
   double* Y = reinterpret_cast<double*>(base + lo.y_off);
-  switch (L) {
-    case 1: return launch_mgs<1>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
-    case 2: return launch_mgs<2>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
-    case 4: return launch_mgs<4>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
+  switch (code) {
+#define PE_C(C_) \
+  case C_: return launch_mgs<C_>(P, N, n, W, lo.w_pt, R, lo.r_pt, Y, lo.y_pt, x, resid, st);
+    PE_C(1) PE_C(2) PE_C(4) PE_C(PE_REAL | 1) PE_C(PE_REAL | 2) PE_C(PE_REAL | 4)
+#undef PE_C
   }
   return hipErrorInvalidValue;
+}
+
+size_t mgs_lds_for(int code, int N) {
+  switch (code) {
+    case 1: return mgs_lds_bytes<1>(N);
+    case 2: return mgs_lds_bytes<2>(N);
+    case 4: return mgs_lds_bytes<4>(N);
+    case PE_REAL | 1: return mgs_lds_bytes<PE_REAL | 1>(N);
+    case PE_REAL | 2: return mgs_lds_bytes<PE_REAL | 2>(N);
+    case PE_REAL | 4: return mgs_lds_bytes<PE_REAL | 4>(N);
+  }
+  return 0;
 }
 
 // The one-workgroup solve (mgs_solve_kernel) for small systems; the
@@ -608,9 +722,8 @@ hipError_t dispatch_mgs(int L, int P, int N, int n, double* W, const NewtonLayou
 // or when the one-workgroup kernel's limits (n + 1 <= 1024, the pivot column
 // in LDS) do not hold.
 bool newton_column_parallel(const pe_system* sys) {
-  const int n = sys->view.n, N = sys->view.N, L = sys->level;
-  const size_t lds = L == 1 ? mgs_lds_bytes<1>(N) : (L == 2 ? mgs_lds_bytes<2>(N) : mgs_lds_bytes<4>(N));
-  return n >= 128 || n + 1 > 1024 || lds > device_lds_limit();
+  const int n = sys->view.n, N = sys->view.N;
+  return n >= 128 || n + 1 > 1024 || mgs_lds_for(sys->code, N) > device_lds_limit();
 }
 
 pe_status newton_check(const pe_system* sys, int P) {
@@ -623,13 +736,14 @@ pe_status newton_check(const pe_system* sys, int P) {
   return PE_OK;
 }
 
-hipError_t dispatch_lstsq(int L, const LsLayout& lo, void* ws, const double* A, int64_t ld, int64_t a_plane,
+hipError_t dispatch_lstsq(int code, const LsLayout& lo, void* ws, const double* A, int64_t ld, int64_t a_plane,
                           int64_t a_pt, double* x, int64_t x_pt, int add, double* resid, double* Rout, double* Qout,
                           hipStream_t st) {
-  switch (L) {
-    case 1: return launch_lstsq<1>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
-    case 2: return launch_lstsq<2>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
-    case 4: return launch_lstsq<4>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
+  switch (code) {
+#define PE_C(C_) \
+  case C_: return launch_lstsq<C_>(lo, ws, A, ld, a_plane, a_pt, x, x_pt, add, resid, Rout, Qout, st);
+    PE_C(1) PE_C(2) PE_C(4) PE_C(PE_REAL | 1) PE_C(PE_REAL | 2) PE_C(PE_REAL | 4)
+#undef PE_C
   }
   return hipErrorInvalidValue;
 }
@@ -640,22 +754,23 @@ extern "C" {
 
 size_t pe_newton_workspace_bytes(const pe_system* sys, int32_t P) {
   if (!sys || P < 0) return 0;
-  const int L = sys->level, N = sys->view.N, n = sys->view.n;
-  if (!newton_column_parallel(sys)) return newton_layout(L, N, n, P).total;
+  const int W = width_of(sys->code), N = sys->view.N, n = sys->view.n;
+  if (!newton_column_parallel(sys)) return newton_layout(W, N, n, P).total;
   // [J | -F] row-major as the evaluation writes it, then the solver's space
-  return align256(size_t(P) * 2 * L * N * (n + 1) * sizeof(double)) + ls_layout(L, N, n, P).total;
+  return align256(size_t(P) * W * N * (n + 1) * sizeof(double)) + ls_layout(sys->code, N, n, P).total;
 }
 
 }  // extern "C"
 
 namespace {
 
-hipError_t dispatch_rhs_shift(int L, double* W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P,
+hipError_t dispatch_rhs_shift(int code, double* W, int64_t w_pt, int64_t plane, int64_t ld, int N, int n, int P,
                               const double* c, double wF, double wc, hipStream_t st) {
-  switch (L) {
-    case 1: return launch_rhs_shift<1>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
-    case 2: return launch_rhs_shift<2>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
-    case 4: return launch_rhs_shift<4>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
+  switch (code) {
+#define PE_C(C_) \
+  case C_: return launch_rhs_shift<C_>(W, w_pt, plane, ld, N, n, P, c, wF, wc, st);
+    PE_C(1) PE_C(2) PE_C(4) PE_C(PE_REAL | 1) PE_C(PE_REAL | 2) PE_C(PE_REAL | 4)
+#undef PE_C
   }
   return hipErrorInvalidValue;
 }
@@ -670,12 +785,12 @@ pe_status newton_step_impl(const pe_system* sys, int32_t P, double* x_inout, con
   if (P == 0) return PE_OK;
   if (!x_inout || !workspace) return fail(PE_EINVAL, "x or workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
-  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  const int code = sys->code, Wd = width_of(code), n = sys->view.n, N = sys->view.N;
   const bool big = newton_column_parallel(sys);
-  const NewtonLayout lo = newton_layout(L, N, n, P);
+  const NewtonLayout lo = newton_layout(Wd, N, n, P);
   char* base = static_cast<char*>(workspace);
   double* W = reinterpret_cast<double*>(base);  // [J | -F], row stride n + 1
-  const int64_t w_pt = int64_t(2) * L * N * (n + 1);
+  const int64_t w_pt = int64_t(Wd) * N * (n + 1);
   hipStream_t hs = static_cast<hipStream_t>(stream);
   OutView O;
   O.J = W;
@@ -690,15 +805,15 @@ pe_status newton_step_impl(const pe_system* sys, int32_t P, double* x_inout, con
   hipError_t e = dispatch_rows(sys, P, x_inout, O, MODE_EVAL, hs);
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton eval launch: ") + hipGetErrorString(e));
   if (c) {
-    e = dispatch_rhs_shift(L, W, w_pt, O.j_plane, n + 1, N, n, P, c, wF, wc, hs);
+    e = dispatch_rhs_shift(code, W, w_pt, O.j_plane, n + 1, N, n, P, c, wF, wc, hs);
     if (e != hipSuccess) return fail(PE_EDEVICE, std::string("homotopy right-hand side: ") + hipGetErrorString(e));
   }
   if (big) {
     void* ls = base + align256(size_t(P) * w_pt * sizeof(double));
-    e = dispatch_lstsq(L, ls_layout(L, N, n, P), ls, W, n + 1, O.j_plane, w_pt, x_inout, int64_t(2) * L * n, 1,
+    e = dispatch_lstsq(code, ls_layout(code, N, n, P), ls, W, n + 1, O.j_plane, w_pt, x_inout, int64_t(Wd) * n, 1,
                        resid_out, nullptr, nullptr, hs);
   } else {
-    e = dispatch_mgs(L, P, N, n, W, lo, base, x_inout, resid_out, hs);
+    e = dispatch_mgs(code, P, N, n, W, lo, base, x_inout, resid_out, hs);
   }
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("newton solve launch: ") + hipGetErrorString(e));
   return PE_OK;
@@ -742,14 +857,20 @@ pe_status pe_homotopy_track(const pe_system* sys, int32_t P, double* x_inout, co
   return PE_OK;
 }
 
+// level codes 1, 2, 4 (complex) and PE_REAL | 1, 2, 4 (real)
+static bool valid_level(int level) {
+  const int L = level & ~PE_REAL;
+  return (level & ~(PE_REAL | 7)) == 0 && (L == 1 || L == 2 || L == 4);
+}
+
 size_t pe_lstsq_workspace_bytes(int32_t level, int32_t P, int32_t N, int32_t n) {
-  if ((level != 1 && level != 2 && level != 4) || P < 0 || N < 1 || n < 1) return 0;
+  if (!valid_level(level) || P < 0 || N < 1 || n < 1) return 0;
   return ls_layout(level, N, n, P).total;
 }
 
 pe_status pe_lstsq(int32_t level, int32_t P, int32_t N, int32_t n, const double* Ab, double* x, double* resid_out,
                    double* R_out, double* Q_out, void* workspace, void* stream) {
-  if (level != 1 && level != 2 && level != 4) return fail(PE_EINVAL, "level must be 1, 2 or 4");
+  if (!valid_level(level)) return fail(PE_EINVAL, "level must be 1, 2 or 4, optionally with PE_REAL");
   if (P < 0 || N < 1 || n < 1) return fail(PE_EINVAL, "need P >= 0, N >= 1, n >= 1");
   if (N < n) return fail(PE_EUNSUPPORTED, "least squares needs N >= n");
   if (N > kLsMaxRows) return fail(PE_EUNSUPPORTED, "the least-squares solve supports at most 4096 rows");
@@ -758,8 +879,9 @@ pe_status pe_lstsq(int32_t level, int32_t P, int32_t N, int32_t n, const double*
   if (!Ab || !x || !workspace) return fail(PE_EINVAL, "Ab, x or workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(PE_EINVAL, "workspace must be 256-byte aligned");
   const int64_t plane = int64_t(N) * (n + 1);
-  hipError_t e = dispatch_lstsq(level, ls_layout(level, N, n, P), workspace, Ab, n + 1, plane, 2 * level * plane, x,
-                                int64_t(2) * level * n, 0, resid_out, R_out, Q_out, static_cast<hipStream_t>(stream));
+  hipError_t e = dispatch_lstsq(level, ls_layout(level, N, n, P), workspace, Ab, n + 1, plane, width_of(level) * plane,
+                                x, int64_t(width_of(level)) * n, 0, resid_out, R_out, Q_out,
+                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("least-squares launch: ") + hipGetErrorString(e));
   return PE_OK;
 }
@@ -773,6 +895,7 @@ pe_status pe_lstsq(int32_t level, int32_t P, int32_t N, int32_t n, const double*
 struct BatchClass {
   int G = 1;  // chunks per workgroup
   int cpl = 1;
+  int vw = 0;  // copy width of batch_small_kernel (0: batch_rows_kernel)
   size_t lds = 0;
   int64_t nitems = 0;
   uint64_t* d_items = nullptr;
@@ -784,10 +907,13 @@ struct pe_batch {
   int S = 0;
   int seg = 4;
   // class 0: systems with a row of two or more chunks (two chunks per
-  // workgroup when compiled and fitting); class 1: the others, one chunk per
-  // workgroup with the LDS of the small systems only, so that several
-  // workgroups share a CU
-  BatchClass cls[2];
+  // workgroup when compiled and fitting); class 1: the other systems with
+  // more than 256 variables, one chunk per workgroup; classes 2..5: systems
+  // whose rows are at most one chunk of at most VW lanes and that have at
+  // most VW variables, VW = 32, 64, 128, 256 (batch_small_kernel, 256 / VW
+  // points per pass)
+  static constexpr int kClasses = 6;
+  BatchClass cls[kClasses];
   int maxN = 0;
   std::vector<const pe_system*> systems;
   std::vector<int64_t> x_off, F_off, J_off;  // per point, doubles, [S+1]
@@ -798,7 +924,7 @@ struct pe_batch {
   int64_t* d_offs = nullptr;  // x_off | F_off | J_off | W offsets, each [S+1]
   BatchNewtonDesc* d_ndesc = nullptr;
   int* d_order = nullptr;
-  int* d_counter = nullptr;  // [2], one per class
+  int* d_counter = nullptr;  // [kClasses], one per class
 };
 
 namespace {
@@ -814,6 +940,7 @@ hipError_t dispatch_batch_class(const pe_batch* b, int c, int P, const double* x
   K.seg = b->seg;
   K.G = C.G;
   K.cpl = C.cpl;
+  K.vw = C.vw;
   K.lds = C.lds;
   K.nitems = C.nitems;
   K.items = C.d_items;
@@ -831,18 +958,19 @@ hipError_t dispatch_batch_class(const pe_batch* b, int c, int P, const double* x
 // reset both queue counters (a kernel, so the launch can be captured), then
 // one persistent launch per non-empty class
 hipError_t dispatch_batch(const pe_batch* b, int P, const double* x, const BatchOut& out, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter, 2);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, b->d_counter, pe_batch::kClasses);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < pe_batch::kClasses; ++c)
     if (b->cls[c].nitems > 0 && (e = dispatch_batch_class(b, c, P, x, out, mode, st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
 void batch_free(pe_batch* b) {
-  for (void* p : {(void*)b->d_views, (void*)b->cls[0].d_items, (void*)b->cls[1].d_items, (void*)b->d_offs,
-                  (void*)b->d_ndesc, (void*)b->d_order, (void*)b->d_counter})
+  for (void* p : {(void*)b->d_views, (void*)b->d_offs, (void*)b->d_ndesc, (void*)b->d_order, (void*)b->d_counter})
     if (p) (void)hipFree(p);
+  for (BatchClass& c : b->cls)
+    if (c.d_items) (void)hipFree(c.d_items);
 }
 
 template <typename T>
@@ -873,6 +1001,11 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     }
   b->level = systems[0]->level;
   b->seg = systems[0]->plan.seg;
+  for (int s = 0; s < S; ++s)
+    if (is_real(systems[s]->code)) {
+      delete b;
+      return fail(PE_EUNSUPPORTED, "batches are implemented for complex systems");
+    }
   b->device = systems[0]->device;
   for (int s = 0; s < S; ++s) {
     const pe_system* y = systems[s];
@@ -884,34 +1017,66 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     b->maxN = std::max(b->maxN, y->view.N);
   }
   const int L = b->level;
-  // classes: systems with a row of two or more chunks (class 0), the others
-  // (class 1); per class the columns, the one-chunk LDS and, for class 0,
-  // two chunks per workgroup when compiled and when every system's table and
-  // two slot regions fit in LDS
+  // classes: systems with a row of two or more chunks (class 0); systems of
+  // one-chunk rows by the copy width VW they need (n and the widest chunk),
+  // classes 2..5 for VW = 32 .. 256, class 1 beyond; per class the columns,
+  // the LDS and, for class 0, two chunks per workgroup when compiled and when
+  // every system's table and two slot regions fit in LDS
+  constexpr int kVw[4] = {32, 64, 128, 256};
   std::vector<int> cls_of(S, 1);
-  int maxcols[2] = {1, 1};
+  int maxcols[pe_batch::kClasses] = {1, 1, 1, 1, 1, 1};
   size_t lds2 = 0;
   bool two_fit = shape_compiled(L, b->seg, 2);
   for (int s = 0; s < S; ++s) {
     const pe_system* y = systems[s];
-    int mc = 0;
+    int mc = 0, wmax = 0;
     for (int p = 0; p < y->view.N; ++p) mc = std::max<int>(mc, y->host.chunk_ptr[p + 1] - y->host.chunk_ptr[p]);
-    const int c = mc >= 2 ? 0 : 1;
+    for (const ChunkDesc& cd : y->host.chunks) wmax = std::max<int>(wmax, cd.width);
+    int c = mc >= 2 ? 0 : 1;
+    if (c == 1)
+      for (int v = 0; v < 4; ++v)
+        if (std::max(y->view.n, wmax) <= kVw[v]) {
+          c = 2 + v;
+          break;
+        }
     cls_of[s] = c;
     maxcols[c] = std::max(maxcols[c], y->view.n);
-    b->cls[c].lds = std::max(b->cls[c].lds, y->plan.lds1);
+    if (c >= 2) {
+      // Q copies of [table][slots][F partials]
+      const int vw = kVw[c - 2];
+      const size_t per_copy = size_t(y->plan.tab_last >= y->plan.tab_first ? y->plan.tab_last - y->plan.tab_first + 1
+                                                                            : 0) * (y->view.n + 1) +
+                              size_t(y->view.max_slots) + size_t(std::max(1, vw / 64));
+      b->cls[c].lds = std::max(b->cls[c].lds, per_copy * 2 * L * sizeof(double) * size_t(kSub / vw));
+    } else {
+      b->cls[c].lds = std::max(b->cls[c].lds, y->plan.lds1);
+    }
     if (c == 0) {
       lds2 = std::max(lds2, lds_bytes<1>(y->view.n, y->view.tab_first, y->view.tab_last, y->view.max_slots, 2) * L);
       two_fit = two_fit && multi_chunk_fits(y->view.n, cpl_bucket(y->view.n, kSub), y->view.max_slots, 2);
     }
   }
-  for (int c = 0; c < 2; ++c) b->cls[c].cpl = cpl_bucket(maxcols[c], kSub);
+  for (int c = 0; c < pe_batch::kClasses; ++c) {
+    b->cls[c].cpl = c >= 2 ? 1 : cpl_bucket(maxcols[c], kSub);
+    b->cls[c].vw = c >= 2 ? kVw[c - 2] : 0;
+  }
   // two chunks per workgroup only when every system of the class fits that
   // shape as pe_eval would run it (same rule), so rows match pe_eval bit for bit
   if (two_fit && lds2 > 0 && lds2 <= device_lds_limit()) {
     b->cls[0].G = 2;
     b->cls[0].lds = lds2;
   }
+  // a small class whose copies do not fit in LDS goes to class 1
+  for (int c = 2; c < pe_batch::kClasses; ++c)
+    if (b->cls[c].lds > device_lds_limit()) {
+      for (int s = 0; s < S; ++s)
+        if (cls_of[s] == c) {
+          cls_of[s] = 1;
+          b->cls[1].lds = std::max(b->cls[1].lds, systems[s]->plan.lds1);
+          b->cls[1].cpl = std::max(b->cls[1].cpl, cpl_bucket(systems[s]->view.n, kSub));
+        }
+      b->cls[c].lds = 0;
+    }
   // packed layout per point
   b->x_off.assign(S + 1, 0);
   b->F_off.assign(S + 1, 0);
@@ -940,8 +1105,8 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   b->y_total = yo;
   // work items of each class in decreasing cost (longest processing time
   // first)
-  std::vector<uint64_t> it[2];
-  for (int c = 0; c < 2; ++c) {
+  std::vector<uint64_t> it[pe_batch::kClasses];
+  for (int c = 0; c < pe_batch::kClasses; ++c) {
     std::vector<std::pair<int64_t, uint64_t>> items;
     for (int s = 0; s < S; ++s) {
       if (cls_of[s] != c) continue;
@@ -952,7 +1117,8 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     for (const auto& pr : items) it[c].push_back(pr.second);
     b->cls[c].nitems = int64_t(it[c].size());
   }
-  b->nitems = b->cls[0].nitems + b->cls[1].nitems;
+  b->nitems = 0;
+  for (const BatchClass& c : b->cls) b->nitems += c.nitems;
   std::vector<SysView> views(S);
   for (int s = 0; s < S; ++s) views[s] = systems[s]->view;
   std::vector<int64_t> offs;
@@ -967,15 +1133,15 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
   });
   hipStream_t hs = static_cast<hipStream_t>(stream);
   pe_status e = PE_OK;
-  if ((e = upload_raw(views, &b->d_views, hs)) != PE_OK || (e = upload_raw(it[0], &b->cls[0].d_items, hs)) != PE_OK ||
-      (e = upload_raw(it[1], &b->cls[1].d_items, hs)) != PE_OK ||
+  for (int c = 0; c < pe_batch::kClasses && e == PE_OK; ++c) e = upload_raw(it[c], &b->cls[c].d_items, hs);
+  if (e != PE_OK || (e = upload_raw(views, &b->d_views, hs)) != PE_OK ||
       (e = upload_raw(offs, &b->d_offs, hs)) != PE_OK || (e = upload_raw(b->ndesc, &b->d_ndesc, hs)) != PE_OK ||
       (e = upload_raw(order, &b->d_order, hs)) != PE_OK) {
     batch_free(b);
     delete b;
     return e;
   }
-  hipError_t he = hipMalloc(reinterpret_cast<void**>(&b->d_counter), 2 * sizeof(int));
+  hipError_t he = hipMalloc(reinterpret_cast<void**>(&b->d_counter), pe_batch::kClasses * sizeof(int));
   if (he == hipSuccess) he = hipStreamSynchronize(hs);
   if (he != hipSuccess) {
     batch_free(b);
@@ -1085,15 +1251,15 @@ pe_status pe_autotune(pe_system* sys, int32_t P, void* stream) {
   if (P < 1) return fail(PE_EINVAL, "P must be positive");
   if (sys->view.N == 0) return PE_OK;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  const int L = sys->level, n = sys->view.n, N = sys->view.N;
-  // inputs: unit-modulus points; outputs F and J
-  const size_t xs = size_t(P) * 2 * L * n, fs = size_t(P) * 2 * L * N, js = fs * n;
+  const int L = sys->level, Wd = width_of(sys->code), n = sys->view.n, N = sys->view.N;
+  // inputs: unit-modulus points (real systems: the cosines); outputs F and J
+  const size_t xs = size_t(P) * Wd * n, fs = size_t(P) * Wd * N, js = fs * n;
   std::vector<double> hx(xs, 0.0);
   for (int pt = 0; pt < P; ++pt)
     for (int j = 0; j < n; ++j) {
       const double t = 0.7 + 0.013 * j + 0.1 * pt;
-      hx[(size_t(pt) * 2 * L + 0) * n + j] = std::cos(t);
-      hx[(size_t(pt) * 2 * L + L) * n + j] = std::sin(t);
+      hx[(size_t(pt) * Wd + 0) * n + j] = std::cos(t);
+      if (!is_real(sys->code)) hx[(size_t(pt) * Wd + L) * n + j] = std::sin(t);
     }
   double *dx = nullptr, *dF = nullptr, *dJ = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;

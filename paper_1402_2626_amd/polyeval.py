@@ -6,6 +6,8 @@ built, importing this module raises ``ImportError``; there is no fallback.
 
 Tensors are float64 and limb-planar: ``x[P, 2, L, n]``, ``F[P, 2, L, N]``,
 ``J[P, 2, L, N, n]`` with L = 1 (double), 2 (double double), 4 (quad double).
+A real system (level ``PE_REAL | L``) has one component instead of two:
+``x[P, 1, L, n]`` and so on.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ _p = ctypes.c_void_p
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
 PE_OK, PE_EINVAL, PE_ENOMEM, PE_EUNSUPPORTED, PE_EDEVICE, PE_ESINGULAR, PE_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+PE_REAL = 8  # level flag of real arithmetic
 
 # every entry point of the C ABI with its ctypes signature
 SIGNATURES = {
@@ -37,6 +40,7 @@ SIGNATURES = {
     "pe_system_info": (_c_int, [_p, _p]),
     "pe_system_set_shape": (_c_int, [_p, _c_int, _c_int, _p]),
     "pe_eval": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
+    "pe_eval_terms": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_eval_adjoint": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_batch_create": (_c_int, [ctypes.POINTER(_p), _c_int, _p, _p]),
     "pe_batch_destroy": (_c_int, [_p]),
@@ -92,7 +96,9 @@ class System:
     """A polynomial system loaded on the current GPU."""
 
     def __init__(self, level: int, n_vars: int, poly_ptr, mon_ptr, var_idx, exps, coef, stream=None):
-        self.level = int(level)
+        self.code = int(level)                 # level code as passed to the library
+        self.level = self.code & ~PE_REAL      # limbs per real part
+        self.ncomp = 1 if self.code & PE_REAL else 2  # components per number
         self.n_vars = int(n_vars)
         self._poly_ptr = np.ascontiguousarray(poly_ptr, dtype=np.int64)
         self._mon_ptr = np.ascontiguousarray(mon_ptr, dtype=np.int64)
@@ -100,8 +106,10 @@ class System:
         self._exps = np.ascontiguousarray(exps, dtype=np.int32)
         self._coef = np.ascontiguousarray(coef, dtype=np.float64)
         self.n_polys = int(self._poly_ptr.shape[0] - 1)
+        self.n_monomials = int(self._mon_ptr.shape[0] - 1)
+        self.nnz = int(self._mon_ptr[-1]) if self.n_monomials > 0 else 0
         h = ctypes.c_void_p()
-        st = _lib.pe_system_create(ctypes.byref(h), self.level, self.n_vars, self.n_polys,
+        st = _lib.pe_system_create(ctypes.byref(h), self.code, self.n_vars, self.n_polys,
                                    self._poly_ptr.ctypes.data, self._mon_ptr.ctypes.data,
                                    self._var_idx.ctypes.data, self._exps.ctypes.data,
                                    self._coef.ctypes.data, _stream(stream) if stream is not False else None)
@@ -147,8 +155,8 @@ class System:
         import torch
         if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous float64 CUDA tensor")
-        if x.dim() != 4 or tuple(x.shape[1:]) != (2, self.level, self.n_vars):
-            raise ValueError(f"x must have shape [P, 2, {self.level}, {self.n_vars}], got {tuple(x.shape)}")
+        if x.dim() != 4 or tuple(x.shape[1:]) != (self.ncomp, self.level, self.n_vars):
+            raise ValueError(f"x must have shape [P, {self.ncomp}, {self.level}, {self.n_vars}], got {tuple(x.shape)}")
 
     def eval(self, x, want_J: bool = True, out=None, stream=None):
         """F (and J) at the points x[P, 2, L, n]."""
@@ -156,13 +164,27 @@ class System:
         self._check_x(x)
         P = x.shape[0]
         if out is None:
-            F = torch.empty((P, 2, self.level, self.n_polys), dtype=torch.float64, device=x.device)
-            J = torch.empty((P, 2, self.level, self.n_polys, self.n_vars), dtype=torch.float64,
+            F = torch.empty((P, self.ncomp, self.level, self.n_polys), dtype=torch.float64, device=x.device)
+            J = torch.empty((P, self.ncomp, self.level, self.n_polys, self.n_vars), dtype=torch.float64,
                             device=x.device) if want_J else None
         else:
             F, J = out
         _check(_lib.pe_eval(self._h, P, _ptr(x), _ptr(F), _ptr(J), _stream(stream)), "pe_eval")
         return F, J
+
+    def eval_terms(self, x, out=None, stream=None):
+        """Every monomial's value V[P, 2, L, M] and partial derivatives
+        G[P, 2, L, nnz] (input order), unsummed."""
+        import torch
+        self._check_x(x)
+        P = x.shape[0]
+        if out is None:
+            V = torch.empty((P, self.ncomp, self.level, self.n_monomials), dtype=torch.float64, device=x.device)
+            G = torch.empty((P, self.ncomp, self.level, self.nnz), dtype=torch.float64, device=x.device)
+        else:
+            V, G = out
+        _check(_lib.pe_eval_terms(self._h, P, _ptr(x), _ptr(V), _ptr(G), _stream(stream)), "pe_eval_terms")
+        return V, G
 
     def adjoint(self, x, v, out=None, stream=None):
         """g = J(x)^H v for x[P, 2, L, n], v[P, 2, L, N]."""
@@ -198,8 +220,8 @@ class System:
         self._check_x(x)
         P = x.shape[0]
         if c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous() or \
-                tuple(c.shape) != (P, 2, self.level, self.n_polys):
-            raise ValueError("c must be a contiguous float64 CUDA tensor [P, 2, L, N]")
+                tuple(c.shape) != (P, self.ncomp, self.level, self.n_polys):
+            raise ValueError("c must be a contiguous float64 CUDA tensor [P, components, L, N]")
         if workspace is None:
             nbytes = self.newton_workspace_bytes(P)
             workspace = torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=x.device)
@@ -295,24 +317,26 @@ class Batch:
 
 
 def lstsq(Ab, want_R: bool = False, want_Q: bool = False, workspace=None, stream=None):
-    """Least-squares solution of A x = b for Ab[P, 2, L, N, n + 1] (float64
-    CUDA, column n = b) by modified Gram-Schmidt on [A b].  Returns
-    (x[P, 2, L, n], resid[P, 2], R[P, 2, L, n, n + 1] or None,
-    Q[P, 2, L, N, n] or None)."""
+    """Least-squares solution of A x = b for Ab[P, C, L, N, n + 1] (float64
+    CUDA, column n = b; C = 2 complex, C = 1 real) by modified Gram-Schmidt
+    on [A b].  Returns (x[P, C, L, n], resid[P, 2], R[P, C, L, n, n + 1] or
+    None, Q[P, C, L, N, n] or None)."""
     import torch
-    if Ab.dtype != torch.float64 or not Ab.is_cuda or not Ab.is_contiguous() or Ab.dim() != 5 or Ab.shape[1] != 2:
-        raise ValueError("Ab must be a contiguous float64 CUDA tensor [P, 2, L, N, n + 1]")
-    P, _, L, N, n1 = Ab.shape
+    if Ab.dtype != torch.float64 or not Ab.is_cuda or not Ab.is_contiguous() or Ab.dim() != 5 or \
+            Ab.shape[1] not in (1, 2):
+        raise ValueError("Ab must be a contiguous float64 CUDA tensor [P, C, L, N, n + 1], C = 2 or 1")
+    P, C, L, N, n1 = Ab.shape
+    code = L | (PE_REAL if C == 1 else 0)
     n = n1 - 1
     dev = Ab.device
-    x = torch.empty((P, 2, L, n), dtype=torch.float64, device=dev)
+    x = torch.empty((P, C, L, n), dtype=torch.float64, device=dev)
     resid = torch.empty((P, 2), dtype=torch.float64, device=dev)
-    R = torch.empty((P, 2, L, n, n + 1), dtype=torch.float64, device=dev) if want_R else None
-    Q = torch.empty((P, 2, L, N, n), dtype=torch.float64, device=dev) if want_Q else None
+    R = torch.empty((P, C, L, n, n + 1), dtype=torch.float64, device=dev) if want_R else None
+    Q = torch.empty((P, C, L, N, n), dtype=torch.float64, device=dev) if want_Q else None
     if workspace is None:
-        nbytes = int(_lib.pe_lstsq_workspace_bytes(L, P, N, n))
+        nbytes = int(_lib.pe_lstsq_workspace_bytes(code, P, N, n))
         workspace = torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=dev)
-    _check(_lib.pe_lstsq(L, P, N, n, _ptr(Ab), _ptr(x), _ptr(resid), _ptr(R), _ptr(Q), _ptr(workspace),
+    _check(_lib.pe_lstsq(code, P, N, n, _ptr(Ab), _ptr(x), _ptr(resid), _ptr(R), _ptr(Q), _ptr(workspace),
                          _stream(stream)), "pe_lstsq")
     return x, resid, R, Q
 

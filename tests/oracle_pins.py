@@ -570,6 +570,73 @@ def pin_error_metric_rejects() -> bool:
     return OE.max_rel_error_rows(sys_, x, Fl, swapped, range(4))[1] > tau
 
 
+# ---------------------------------------------------------------- terms
+
+def pin_terms_closed_form() -> bool:
+    """Terms in the input order (Sec. 2.2 Tables 1-2 output, Sec. 2.3 factors):
+    the monomial 3 x_3^2 x_0 x_1^3 written with its variables out of order, at
+    x = (2, 5, 0, -1): value 3 * 1 * 2 * 125 = 750 and the partials in the
+    input order d/dx_3 = 3 * 2 x_3 x_0 x_1^3 = -1500, d/dx_0 = 3 x_3^2 x_1^3 =
+    375, d/dx_1 = 3 * 3 x_3^2 x_0 x_1^2 = 450; a constant term has no
+    partial; complex data: (2i) x_2 at x_2 = 1 + i gives -2 + 2i and 2i."""
+    sys_ = synth.from_monomial_lists(1, 4, [[(3.0, [(3, 2), (0, 1), (1, 3)]), (7.0, [])],
+                                             [(2j, [(2, 1)])]])
+    x = np.zeros((2, 1, 4))
+    x[0, 0] = [2.0, 5.0, 1.0, -1.0]
+    x[1, 0, 2] = 1.0
+    T = O.eval_terms(sys_, x, range(3))
+    v0, g0 = T[0]
+    if O.cdy_to_complex(v0) != 750 or [O.cdy_to_complex(g) for g in g0] != [-1500, 375, 450]:
+        return False
+    v1, g1 = T[1]
+    if O.cdy_to_complex(v1) != 7 or g1 != []:
+        return False
+    v2, g2 = T[2]
+    return O.cdy_to_complex(v2) == -2 + 2j and [O.cdy_to_complex(g) for g in g2] == [2j]
+
+
+def pin_terms_euler() -> bool:
+    """Euler's identity per term: sum_r x_{i_r} dT/dx_{i_r} = (sum_r d_r) T,
+    exactly, for every monomial of a random double-double system with
+    exponents up to 4 and variables in shuffled input order."""
+    rng = synth.rng_for(71)
+    sys_ = synth.random_system(72, 2, n_vars=9, n_polys=4, m=5, k=4, exp_lo=1, exp_hi=4)
+    perm = np.concatenate([rng.permutation(np.arange(a, b)) for a, b in zip(sys_.mon_ptr[:-1], sys_.mon_ptr[1:])])
+    sys_.var_idx = sys_.var_idx[perm]
+    sys_.exps = sys_.exps[perm]
+    x = synth.unit_circle_points(synth.rng_for(73), 1, 9, 2)[0]
+    X = O.point_from_limbs(x)
+    T = O.eval_terms(sys_, x, range(sys_.n_monomials))
+    for t, (v, g) in T.items():
+        vs, ds = sys_.monomial(t)
+        acc = O.ZERO
+        for r, j in enumerate(vs):
+            acc = O.cdy_add(acc, O.cdy_mul(X[int(j)], g[r]))
+        if not O.cdy_is_zero(O.cdy_add(acc, O.cdy_neg(O.cdy_scale(v, int(sum(int(d) for d in ds)))))):
+            return False
+    return True
+
+
+def pin_terms_abs() -> bool:
+    """The terms' normalisers equal the moduli of the terms when every
+    coefficient and every variable is positive (then |term| = term)."""
+    sys_ = synth.random_system(74, 1, n_vars=6, n_polys=3, m=4, k=3, exp_lo=1, exp_hi=3)
+    c = np.zeros_like(sys_.coef)
+    c[0, 0] = np.linspace(0.25, 2.0, sys_.n_monomials)
+    sys_.coef = c
+    x = np.zeros((2, 1, 6))
+    x[0, 0] = [0.5, 1.25, 2.0, 0.75, 1.5, 1.0]
+    T = O.eval_terms(sys_, x, range(sys_.n_monomials))
+    A = O.abs_terms(sys_, x, range(sys_.n_monomials))
+    for t, (v, g) in T.items():
+        sv, sg = A[t]
+        if abs(O.cdy_to_complex(v).real - sv) > 1e-12 * sv:
+            return False
+        if any(abs(O.cdy_to_complex(gi).real - s) > 1e-12 * s for gi, s in zip(g, sg)):
+            return False
+    return True
+
+
 ALL_PINS = [
     pin_speelpenning_closed_form, pin_speelpenning_figures, pin_speelpenning_euler,
     pin_linear_system, pin_linear_adjoint, pin_univariate, pin_univariate_mpmath,
@@ -578,4 +645,7 @@ ALL_PINS = [
     pin_gauss_newton_linear, pin_gauss_newton_quadratic, pin_columns_match_rows,
     pin_abs_sums_positive, pin_error_metric_rejects, pin_lstsq_limbs, pin_homotopy_square_root,
     pin_homotopy_decoupled_squares,
+    pin_terms_closed_form,
+    pin_terms_euler,
+    pin_terms_abs,
 ]

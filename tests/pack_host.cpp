@@ -68,3 +68,9 @@ extern "C" void pe_test_pack_get(int64_t* chunks, uint16_t* occ /* [occ][4] */, 
   std::memcpy(mcoef, g_packed.mcoef.data(), g_packed.mcoef.size() * 8);
   std::memcpy(chunk_ptr, g_packed.chunk_ptr.data(), g_packed.chunk_ptr.size() * 4);
 }
+
+// input-order maps: [M] monomial indices, [occ] occurrence indices
+extern "C" void pe_test_pack_orig(uint32_t* mon_orig, uint32_t* occ_orig) {
+  std::memcpy(mon_orig, g_packed.mon_orig.data(), g_packed.mon_orig.size() * 4);
+  std::memcpy(occ_orig, g_packed.occ_orig.data(), g_packed.occ_orig.size() * 4);
+}

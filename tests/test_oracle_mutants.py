@@ -284,6 +284,54 @@ def _make_homotopy_step_sign():
     return homotopy_step_mp
 
 
+def _make_terms_sorted_order():
+    orig = E.eval_terms
+
+    def eval_terms(sys_, x, monomials):
+        # partials in increasing variable order instead of the input order
+        out = orig(sys_, x, monomials)
+        res = {}
+        for t, (v, g) in out.items():
+            vs, _ = sys_.monomial(t)
+            order = sorted(range(len(vs)), key=lambda r: int(vs[r]))
+            res[t] = (v, [g[r] for r in order])
+        return res
+    return eval_terms
+
+
+def _make_terms_no_coefficient():
+    def eval_terms(sys_, x, monomials):
+        X = E.point_from_limbs(x)
+        out = {}
+        for t in monomials:
+            vs, ds = sys_.monomial(int(t))
+            out[int(t)] = E.monomial_value_and_partials(E.ONE, [X[int(v)] for v in vs], ds)  # c_t dropped
+        return out
+    return eval_terms
+
+
+def _mut_abs_terms_no_exponent(sys_, x, monomials):
+    import numpy as np
+    ax = np.hypot(x[0].sum(axis=0), x[1].sum(axis=0))
+    out = {}
+    for t in monomials:
+        vs, ds = sys_.monomial(int(t))
+        ac = float(np.hypot(sys_.coef[0, :, int(t)].sum(), sys_.coef[1, :, int(t)].sum()))
+        pw = [float(ax[int(v)]) ** int(d) for v, d in zip(vs, ds)]
+        val = ac
+        for q in pw:
+            val *= q
+        parts = []
+        for r, (v, d) in enumerate(zip(vs, ds)):
+            g = ac * float(ax[int(v)]) ** (int(d) - 1)  # exponent factor d dropped
+            for q in range(len(vs)):
+                if q != r:
+                    g *= pw[q]
+            parts.append(g)
+        out[int(t)] = (val, parts)
+    return out
+
+
 MUTANTS = {
     "power_off_by_one": ("_power", _mut_power_off_by_one),
     "mul_sign": ("cdy_mul", _mut_mul_sign),
@@ -306,13 +354,20 @@ MUTANTS = {
     "lstsq_transpose_not_adjoint": ("_lstsq_householder", _mut_lstsq_transpose),
     "abs_values_no_power": ("abs_sums_values", _mut_abs_values_no_power),
     "homotopy_sign": ("homotopy_step_mp", _make_homotopy_step_sign()),
+    "terms_sorted_order": ("eval_terms", _make_terms_sorted_order()),
+    "terms_no_coefficient": ("eval_terms", _make_terms_no_coefficient()),
+    "abs_terms_no_exponent": ("abs_terms", _mut_abs_terms_no_exponent),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, monkeypatch):
+    import oracle
     attr, fn = MUTANTS[name]
     monkeypatch.setattr(E, attr, fn)
+    # the package re-exports the module's names: the pins see the mutant too
+    if hasattr(oracle, attr):
+        monkeypatch.setattr(oracle, attr, fn)
     failed = []
     for pin in pins.ALL_PINS:
         try:

@@ -150,3 +150,72 @@ def test_packer_under_sanitizers(tmp_path):
     env.pop("LD_PRELOAD", None)
     run = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=600)
     assert run.returncode == 0 and run.stdout.strip().endswith("OK"), run.stdout[-2000:] + run.stderr[-4000:]
+
+
+def _orig_maps(lib, P, M):
+    mon = np.zeros(M, np.uint32)
+    occ = np.zeros(P["occ"].shape[0], np.uint32)
+    lib.pe_test_pack_orig(ctypes.c_void_p(mon.ctypes.data), ctypes.c_void_p(occ.ctypes.data))
+    return mon, occ
+
+
+@pytest.mark.parametrize("seg", [2, 4, 8])
+def test_pack_input_order_maps(lib, seg):
+    """The maps behind the per-monomial output: every input monomial appears
+    once among the packed monomials; every record's input occurrence names
+    the record's variable and exponent and lies in its monomial's input
+    range; neutral records map to no occurrence; every occurrence is named
+    exactly once (variables shuffled within monomials)."""
+    s = synth.random_system(21, 2, n_vars=50, n_polys=7, m=30, k=9, exp_lo=1, exp_hi=4)
+    rng = synth.rng_for(22)
+    perm = np.concatenate([rng.permutation(np.arange(a, b)) for a, b in zip(s.mon_ptr[:-1], s.mon_ptr[1:])])
+    s.var_idx = np.ascontiguousarray(s.var_idx[perm])
+    s.exps = np.ascontiguousarray(s.exps[perm])
+    P = pack(lib, s, seg)
+    mon, occ = _orig_maps(lib, P, s.n_monomials)
+    assert sorted(mon.tolist()) == list(range(s.n_monomials))
+    seen = np.zeros(s.nnz, np.int64)
+    for ch in P["chunks"]:
+        occ_base, mon_base, _, _, count, nslots, width, lanes, segc = (int(v) for v in ch)
+        for i in range(segc):
+            for lam in range(width):
+                r = occ_base + i * width + lam
+                o = int(occ[r])
+                var, ex, slot = int(P["occ"][r][0]), int(P["occ"][r][1]), int(P["occ"][r][2])
+                if slot == nslots:
+                    assert o == 0xFFFFFFFF
+                    continue
+                t = int(mon[mon_base + lam // lanes])
+                assert s.mon_ptr[t] <= o < s.mon_ptr[t + 1]
+                assert int(s.var_idx[o]) == var and int(s.exps[o]) == ex
+                seen[o] += 1
+    assert np.all(seen == 1)
+
+
+def test_pack_real_coefficients(lib):
+    """A real system (level 8 | L) packs one component per coefficient: the
+    packed coefficients are the input's limbs in packed monomial order."""
+    s = synth.random_system(23, 2, n_vars=20, n_polys=5, m=9, k=4)
+    coef_real = np.ascontiguousarray(s.coef[:1])
+    arrs = [np.ascontiguousarray(a) for a in (s.poly_ptr, s.mon_ptr, s.var_idx, s.exps, coef_real)]
+    sizes = np.zeros(9, np.int64)
+    st = lib.pe_test_pack(8 | 2, s.n_vars, s.n_polys, *[ctypes.c_void_p(a.ctypes.data) for a in arrs], 4, 1152,
+                          ctypes.c_void_p(sizes.ctypes.data))
+    assert st == 0, lib.pe_test_pack_msg()
+    nch, nocc, ncol, M = int(sizes[0]), int(sizes[1]), int(sizes[2]), int(sizes[3])
+    chunks = np.zeros((nch, 9), np.int64)
+    occ = np.zeros((nocc, 4), np.uint16)
+    colptr = np.zeros(ncol, np.uint16)
+    mmeta = np.zeros(M, np.uint32)
+    mcoef = np.zeros(M * 2 * 2)  # room for the complex layout; a real one fills half
+    cptr = np.zeros(s.n_polys + 1, np.uint32)
+    lib.pe_test_pack_get(*[ctypes.c_void_p(a.ctypes.data) for a in (chunks, occ, colptr, mmeta, mcoef, cptr)])
+    mon, _ = _orig_maps(lib, dict(occ=occ), M)
+    for tp in range(M):
+        t = int(mon[tp])
+        assert np.array_equal(mcoef[2 * tp:2 * tp + 2], s.coef[0, :, t])
+    assert np.all(mcoef[2 * M:] == 0.0)
+    # an invalid level code is refused
+    st = lib.pe_test_pack(16 | 2, s.n_vars, s.n_polys, *[ctypes.c_void_p(a.ctypes.data) for a in arrs], 4, 1152,
+                          ctypes.c_void_p(sizes.ctypes.data))
+    assert st == -1
