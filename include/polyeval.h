@@ -182,6 +182,25 @@ pe_status pe_eval_terms(const pe_system* sys, int32_t P, const double* x, double
 pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, const double* v,
                           double* g, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the adjoint above with its
+ * partial rows in a static device array of PE_STATIC_SCRATCH_BYTES per GPU
+ * (reserved when the library's code is loaded on a GPU, held until the
+ * process ends) instead of a per-system workspace.  Allocates nothing and
+ * never synchronises, on every call.  Arguments, layouts and results as in
+ * pe_eval_adjoint; the GPU is the calling thread's current device.  The
+ * workgroups take the same groups of polynomials as pe_eval_adjoint (so the
+ * results are bitwise the same) when their partial rows fit in the array,
+ * otherwise fewer, larger groups (the same values up to rounding).
+ * PE_EUNSUPPORTED when one partial row per point, P * 16 L * n bytes, does
+ * not fit.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on a GPU (different streams, or host threads) race and give wrong results;
+ * serialise them.  The array needs no clearing (every call writes every
+ * partial it reads). */
+#define PE_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+pe_status pe_eval_adjoint_static(const pe_system* sys, int32_t P, const double* x, const double* v,
+                                 double* g, void* stream);
+
 /* ------------------------------------------------------------------ batches
  * A batch evaluates S independent systems of the same level, each at the
  * same number of points, in persistent launches whose work items

@@ -668,6 +668,88 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ adjoint without allocation
+
+namespace {
+
+// The partial rows of pe_eval_adjoint_static live in this array: one copy
+// per GPU, held until the process ends, shared by every call on that GPU.
+// In host code its name is not a device address; host code uses only the
+// per-device address that hipGetSymbolAddress returns (static_scratch).
+constexpr size_t kStaticScratchBytes = PE_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the address of `scratch` on the calling thread's current device, looked up
+// once per device
+pe_status static_scratch(double** out) {
+  int dev = 0;
+  PE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PE_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PE_EDEVICE, std::string("address of the static scratch array: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PE_OK;
+}
+
+// g = 0 for a system without polynomials (a kernel, not a memset node, so
+// that the call can be captured in a graph)
+__global__ void zero_fill_kernel(double* __restrict__ a, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+pe_status pe_eval_adjoint_static(const pe_system* sys, int32_t P, const double* x, const double* v, double* g,
+                                 void* stream) {
+  if (!sys) return fail(PE_EINVAL, "system is NULL");
+  if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
+  if (P == 0) return PE_OK;
+  if (!x || !v || !g) return fail(PE_EINVAL, "x, v or g is NULL");
+  if (is_real(sys->code)) return fail(PE_EUNSUPPORTED, "the adjoint is implemented for complex systems");
+  const int L = sys->level, n = sys->view.n, N = sys->view.N;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const size_t row_bytes = size_t(P) * 2 * L * n * sizeof(double);  // one partial row per point
+  if (row_bytes > kStaticScratchBytes)
+    return fail(PE_EUNSUPPORTED, "P * 16 L * n bytes exceed the static scratch of pe_eval_adjoint_static (" +
+                                     std::to_string(kStaticScratchBytes >> 20) + " MiB)");
+  if (N == 0) {
+    const int64_t cnt = int64_t(P) * 2 * L * n;
+    hipLaunchKernelGGL(zero_fill_kernel, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, hs, g, cnt);
+    PE_HIP(hipGetLastError());
+    return PE_OK;
+  }
+  double* part = nullptr;
+  pe_status ps = static_scratch(&part);
+  if (ps != PE_OK) return ps;
+  // the groups of pe_eval_adjoint when their partial rows fit, else fewer
+  // and larger groups
+  int NG = 0, gsize = 0;
+  adjoint_groups(N, P, NG, gsize);
+  const int ng_fit = int(std::min<size_t>(kStaticScratchBytes / row_bytes, size_t(N)));
+  if (NG > ng_fit) {
+    gsize = (N + ng_fit - 1) / ng_fit;
+    NG = (N + gsize - 1) / gsize;
+  }
+  hipError_t e = dispatch_adj(sys, P, x, v, NG, gsize, part, g, hs);
+  if (e != hipSuccess) return fail(PE_EDEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
+  return PE_OK;
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------------ Newton
 
 namespace {

@@ -42,6 +42,7 @@ SIGNATURES = {
     "pe_eval": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_eval_terms": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_eval_adjoint": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
+    "pe_eval_adjoint_static": (_c_int, [_p, _c_int, _p, _p, _p, _p]),
     "pe_batch_create": (_c_int, [ctypes.POINTER(_p), _c_int, _p, _p]),
     "pe_batch_destroy": (_c_int, [_p]),
     "pe_batch_layout": (_c_int, [_p, _p, _p, _p]),
@@ -196,6 +197,19 @@ class System:
         g = torch.empty_like(x) if out is None else out
         _check(_lib.pe_eval_adjoint(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(g), _stream(stream)),
                "pe_eval_adjoint")
+        return g
+
+    def adjoint_static(self, x, v, out=None, stream=None):
+        """g = J(x)^H v through pe_eval_adjoint_static (no allocation in the
+        library; calls on one GPU must not overlap)."""
+        import torch
+        self._check_x(x)
+        if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous() or \
+                tuple(v.shape) != (x.shape[0], 2, self.level, self.n_polys):
+            raise ValueError("v must be a contiguous float64 CUDA tensor [P, 2, L, N]")
+        g = torch.empty_like(x) if out is None else out
+        _check(_lib.pe_eval_adjoint_static(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(g), _stream(stream)),
+               "pe_eval_adjoint_static")
         return g
 
     def newton_workspace_bytes(self, P: int) -> int:
