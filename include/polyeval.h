@@ -96,9 +96,9 @@ const char* pe_last_error(void);
  * are allowed; duplicate monomials are kept as given (never merged).
  * Size limits (PE_EUNSUPPORTED beyond them): n <= 2048 variables; a
  * monomial spans at most one wavefront of 64 lanes, so it has at most
- * 64 * segment variables: 1024 in double (segment 16), 512 in double double
- * (segment 8), 256 in quad double (segment 4); at most 2^31 monomials and
- * 2^32 occurrences.  (n > 65535 and monomials over 1024 variables are
+ * 64 * segment variables: 1024 in double and double double (segment 16),
+ * 512 in quad double (segment 8); systems with monomials that wide get that
+ * segment by default; at most 2^31 monomials and 2^32 occurrences.  (n > 65535 and monomials over 1024 variables are
  * rejected by the validation itself.)
  * Returns PE_EINVAL for malformed input (out-of-range index, exponent < 1,
  * duplicate variable in a monomial, non-monotone offsets), PE_EUNSUPPORTED
@@ -125,13 +125,15 @@ pe_status pe_system_info(const pe_system* sys, int64_t info[11]);
  * monomials of a row are cut into chunks of 256 lanes, and a workgroup of
  * chunks_per_workgroup * 256 threads works on that many chunks of a row at
  * once, adding their partial rows in a fixed order.
- *   segment               variables per lane: 8 or 16 (D), 4, 6 or 8 (DD),
- *                         2 or 4 (QD); 0 = the default: the first of 8, 16
- *                         (D), 8, 6, 4 (DD) or 4, 2 (QD) for which the most
- *                         common monomial size k is an exact multiple of s
- *                         filling every lane (k > (segment - 1) * s), else 8
- *                         (D, DD) or 4 (QD).  pe_system_create starts from
- *                         the same default.
+ *   segment               variables per lane: 8 or 16 (D), 4, 6, 8 or 16
+ *                         (DD), 2, 4 or 8 (QD); 0 = the default: the first of
+ *                         8, 16 (D), 8, 6, 4 (DD) or 4, 2 (QD) for which the
+ *                         most common monomial size k is an exact multiple of
+ *                         s filling every lane (k > (segment - 1) * s), else 8
+ *                         (D, DD) or 4 (QD); then widened to the shortest
+ *                         compiled segment that fits the largest monomial in
+ *                         64 lanes.  pe_system_create starts from the same
+ *                         default.
  *   chunks_per_workgroup  1, 2 or 4 as compiled for the level and segment;
  *                         0 = the largest that fits.
  * A new segment length repacks the system (host work and a device upload

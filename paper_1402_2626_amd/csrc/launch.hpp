@@ -15,7 +15,9 @@ namespace pe {
 
 // The compiled launch shapes (level, segment length, chunks per workgroup).
 // A workgroup of G chunks has G * 256 threads; G > 1 is compiled for up to
-// 512 columns only.
+// 512 columns only.  Double double with segments of 16 and quad double with
+// segments of 8 exist for monomials too wide for the shorter segments (up to
+// 1024 and 512 variables in one wavefront); they hold many registers per lane.
 #define PE_SHAPES(X) \
   X(1, 8, 1)         \
   X(1, 8, 4)         \
@@ -27,8 +29,10 @@ namespace pe {
   X(2, 6, 2)         \
   X(2, 8, 1)         \
   X(2, 8, 2)         \
+  X(2, 16, 1)        \
   X(4, 4, 1)         \
-  X(4, 2, 1)
+  X(4, 2, 1)         \
+  X(4, 8, 1)
 
 inline bool shape_compiled(int L, int seg, int G) {
 #define PE_X(L_, S_, G_) \

@@ -62,12 +62,23 @@ int default_seg_for(int L, const std::vector<int64_t>& mon_ptr) {
   static const int pref1[] = {8, 16}, pref2[] = {8, 6, 4}, pref4[] = {4, 2};
   const int* pref = L == 1 ? pref1 : (L == 2 ? pref2 : pref4);
   const int np = L == 1 ? 2 : (L == 2 ? 3 : 2);
+  int chosen = default_seg(L);
   for (int i = 0; i < np; ++i) {
     const int seg = pref[i];
     const int s = lanes_for(kmode, seg);
-    if (s <= kMaxWave && (kmode + s - 1) / s == seg) return seg;
+    if (s <= kMaxWave && (kmode + s - 1) / s == seg) {
+      chosen = seg;
+      break;
+    }
   }
-  return default_seg(L);
+  // a monomial must fit in one wavefront: the shortest compiled segment that
+  // holds the largest monomial, when the chosen one does not
+  int kmax = 0;
+  for (size_t t = 0; t + 1 < mon_ptr.size(); ++t) kmax = std::max<int>(kmax, int(mon_ptr[t + 1] - mon_ptr[t]));
+  if (kmax > 0 && lanes_for(kmax, chosen) > kMaxWave)
+    for (int seg : {2, 4, 6, 8, 16})
+      if (shape_compiled(L, seg, 1) && lanes_for(kmax, seg) <= kMaxWave) return seg;
+  return chosen;
 }
 
 int default_slots(int L) { return L == 1 ? 2304 : (L == 2 ? 1152 : 1088); }

@@ -61,6 +61,9 @@ GOOD = dict(level=2, n=4, poly_ptr=[0, 2], mon_ptr=[0, 2, 3], var_idx=[0, 3, 1],
 
 @pytest.mark.parametrize("change, status, words", [
     (dict(level=3), -1, "level"),
+    (dict(level=16 | 2), -1, "level"),
+    (dict(level=8 | 3), -1, "level"),
+    (dict(level=8 | 2, var_idx=[0, 4, 1]), -1, "out of range"),
     (dict(n=0), -1, "n_vars"),
     (dict(n=70000), -3, "65535"),
     (dict(var_idx=[0, 4, 1]), -1, "out of range"),
@@ -80,6 +83,20 @@ def test_validation_errors(lib, change, status, words):
     assert st == status, msg
     assert words in msg
     assert not h.value
+
+
+def test_lstsq_level_codes(lib):
+    """pe_lstsq takes the level codes 1, 2, 4 and PE_REAL | 1, 2, 4; other
+    codes are refused before any device work (workspace size 0, PE_EINVAL)."""
+    lib.pe_lstsq_workspace_bytes.restype = ctypes.c_size_t
+    lib.pe_lstsq.restype = ctypes.c_int32
+    for code in (1, 2, 4, 9, 10, 12):
+        assert lib.pe_lstsq_workspace_bytes(code, 1, 10, 5) > 0
+    for code in (0, 3, 8, 11, 18):
+        assert lib.pe_lstsq_workspace_bytes(code, 1, 10, 5) == 0
+        assert lib.pe_lstsq(code, 1, 10, 5, None, None, None, None, None, None, None) == -1
+    # real workspaces are smaller than complex ones (one component)
+    assert lib.pe_lstsq_workspace_bytes(10, 1, 100, 50) < lib.pe_lstsq_workspace_bytes(2, 1, 100, 50)
 
 
 def test_null_arguments(lib):

@@ -1,0 +1,82 @@
+"""Monomials wider than the default segment allows: double double up to 1024
+variables (segment 16) and quad double up to 512 (segment 8), chosen by
+default when a system needs them; cyclic n-roots in quad double at n = 448
+(the largest QD case of the paper's Table 5)."""
+import numpy as np
+import pytest
+
+import gpu_util as U
+import oracle as O
+from paper_1402_2626_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pe():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1402_2626_amd import polyeval
+    return polyeval
+
+
+def test_cyclic_qd_448(pe):
+    """Cyclic 448-roots (eq. (5)) in complex quad double: the default segment
+    becomes 8 (monomials of up to 448 variables in 56 lanes); at x = 1 F and
+    J equal their closed forms bit for bit (F_i = n for i < n, F_n = 0,
+    J_{i,m} = i, last row all ones); at a random unit-circle point sampled
+    rows match the oracle (full rows where monomials are short, F and four
+    columns on the long rows up to the longest)."""
+    import torch
+    n, L = 448, 4
+    sys_ = synth.cyclic_roots_system(n, L)
+    S = pe.System.from_sparse(sys_)
+    assert S.info()["segment"] == 8
+    one = np.zeros((1, 2, L, n))
+    one[0, 0, 0] = 1.0
+    F, J = S.eval(U.to_device(one))
+    torch.cuda.synchronize()
+    F, J = F.cpu().numpy()[0], J.cpu().numpy()[0]
+    wantF = np.zeros((2, L, n))
+    wantF[0, 0, :n - 1] = n
+    assert np.array_equal(F, wantF)
+    wantJ = np.zeros((2, L, n, n))
+    wantJ[0, 0, :n - 1, :] = np.arange(1, n)[:, None]
+    wantJ[0, 0, n - 1, :] = 1.0
+    assert np.array_equal(J, wantJ)
+    x = synth.unit_circle_points(synth.rng_for((0, 1)), 1, n, L)
+    F, J = S.eval(U.to_device(x))
+    torch.cuda.synchronize()
+    S.close()
+    F, J = F.cpu().numpy()[0], J.cpu().numpy()[0]
+    picks = {r: range(n) for r in (0, 1, 4, 15)}
+    for r in (63, 200, 300, 445, 446, 447):
+        picks[r] = [0, r // 2, (r + 7) % n, n - 1]
+    U.flush(f"cyclic448 QD random point: oracle over {len(picks)} rows")
+    eF, eJ = U.max_errors_entries(sys_, x[0], F, J, picks)
+    tol = U.tolerance(sys_)
+    U.flush(f"cyclic448 QD: eF={eF:.2e} eJ={eJ:.2e} tol={tol:.1e}")
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("level, k, seg", [(2, 1024, 16), (2, 700, 16), (4, 512, 8), (4, 300, 8)])
+def test_wide_monomials(pe, level, k, seg):
+    """Products of k variables (exponent 1) at the level's widest segment,
+    three polynomials of two monomials each at a random point: every row
+    against the oracle, and Euler's identity sum_j x_j J_pj = k F_p on the
+    exact values."""
+    import torch
+    n = 1024 if k > 512 else 512
+    sys_ = synth.random_system((751, level, k), level, n_vars=n, n_polys=3, m=2, k=k, exp_lo=1, exp_hi=1)
+    S = pe.System.from_sparse(sys_)
+    assert S.info()["segment"] == seg
+    x = synth.unit_circle_points(synth.rng_for((752, k)), 1, n, level)
+    F, J = S.eval(U.to_device(x))
+    torch.cuda.synchronize()
+    S.close()
+    F, J = F.cpu().numpy()[0], J.cpu().numpy()[0]
+    picks = {p: [0, 1, n // 2, n - 1] + list(range(5, n, 97)) for p in range(3)}
+    eF, eJ = U.max_errors_entries(sys_, x[0], F, J, picks)
+    tol = U.tolerance(sys_)
+    assert eF <= tol and eJ <= tol, (eF, eJ, tol)
