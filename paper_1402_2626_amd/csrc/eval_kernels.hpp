@@ -937,7 +937,9 @@ __device__ __forceinline__ OutView batch_out_view(const BatchOut& out, int s, in
 // table, slot region and F partials in LDS; lane v of a copy does what lane
 // v of a one-chunk workgroup of eval_rows_kernel does (the same records, the
 // same monomial phase, the same owner column v), so every row equals
-// pe_eval's bit for bit.  The records are loaded once per row.  Every
+// pe_eval's bit for bit.  The records are loaded again for every pass (an
+// L2 hit): kept in registers across the passes they pushed the kernel past
+// the 256 registers of two wavefronts per SIMD and into scratch.  Every
 // workgroup reaches the exit test after every item, so the grid drains.
 template <int L, int SEG, int VW, int MODE>
 __global__ __launch_bounds__(kSub, 2) void batch_small_kernel(const SysView* __restrict__ views,
@@ -969,10 +971,10 @@ __global__ __launch_bounds__(kSub, 2) void batch_small_kernel(const SysView* __r
     double* contrib = tab + tab_doubles(S, L);
     double* fpart = contrib + size_t(S.max_slots) * width_of(L);
     const uint32_t ch0 = S.chunk_ptr[p], ch1 = S.chunk_ptr[p + 1];
-    ChunkLoads<L, SEG, 1> cl;
-    load_chunk<L, SEG, 1, MODE>(S, ch0, ch0 < ch1, lv, nullptr, cl);
     const double* xs = x + x_off[s] * P;
     for (int pt0 = 0; pt0 < P; pt0 += Q) {
+      ChunkLoads<L, SEG, 1> cl;
+      load_chunk<L, SEG, 1, MODE>(S, ch0, ch0 < ch1, lv, nullptr, cl);
       const int pt = pt0 + qi;
       const bool live = pt < P;
       const double* xpt = xs + int64_t(live ? pt : 0) * width_of(L) * n;
