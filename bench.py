@@ -443,10 +443,9 @@ def bench_newton_single(args):
     J = torch.empty((1, 2, 2, 256, 256), dtype=torch.float64, device="cuda")
     _, ms_eval = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, Wm, st)
     S.close()
-    # the solve's complex multiply-adds: MGS on 256 x 257 (about 2 N n^2) and
-    # back substitution
+    from paper_1402_2626_amd import workmodel as WM
     n = 256
-    cmadd = 2.0 * n * n * (n + 1) + n * n
+    cmadd = WM.lstsq_multiply_adds(n, n)
     out = line("Gauss-Newton step, complex double-double, 256 x 256 system with a planted root (evaluation, "
                "least squares by modified Gram-Schmidt, update)", 2, sys_.n_monomials * K / dt, K, Wm, dt,
                {"name": "newton_dd_n256", "kernel_ms": ms, "eval_ms": ms_eval,
@@ -563,6 +562,72 @@ def bench_real_qd_chandrasekhar(args):
     print(json.dumps(out), flush=True)
 
 
+# the paper's Newton runs on Chandrasekhar's H-equation: Table 3 (six
+# iterations, complex double double) and Table 4 (seven iterations, real quad
+# double); its accelerated wall-clock times in seconds, context only
+TABLE3_GPU2_S = {1024: 20.083, 2048: 149.770, 3072: 495.565, 4096: 1164.243}
+TABLE4_GPU_S = {1016: 59.570, 2032: 402.595, 3048: 1281.047, 4064: 2542.440}
+
+
+def bench_newton_tables(args, table):
+    """All iterations of the paper's Newton runs on the H-equation from
+    H = 1, evaluation and least squares on the GPU, one line per dimension."""
+    import numpy as np
+    import torch
+    from paper_1402_2626_amd import polyeval as pe
+    from paper_1402_2626_amd import synth
+
+    from paper_1402_2626_amd import workmodel as WM
+
+    real = table == 4
+    L, iters, ref = (4, 7, TABLE4_GPU_S) if real else (2, 6, TABLE3_GPU2_S)
+    for n in sorted(ref):
+        sys_ = synth.chandrasekhar_system(n, L)
+        if real:
+            S = pe.System(pe.PE_REAL | L, n, sys_.poly_ptr, sys_.mon_ptr, sys_.var_idx, sys_.exps,
+                          np.ascontiguousarray(sys_.coef[:1]))
+        else:
+            S = pe.System.from_sparse(sys_)
+        C = 1 if real else 2
+        x = torch.zeros((1, C, L, n), dtype=torch.float64, device="cuda")
+        x[0, 0, 0] = 1.0
+        ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+        resid = torch.empty((1, 2), dtype=torch.float64, device="cuda")
+        st = torch.cuda.current_stream()
+        x0 = x.clone()
+        S.newton_step(x, workspace=ws, resid=resid, stream=st)  # warm-up (kernel loading)
+        torch.cuda.synchronize()
+        x.copy_(x0)
+        res = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(iters):
+            S.newton_step(x, workspace=ws, resid=resid, stream=st)
+            res.append(resid.clone())
+        e1.record(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        S.close()
+        norms = [float(r[0, 0]) for r in res]
+        steps = [float(r[0, 1]) for r in res]
+        kms = e0.elapsed_time(e1)
+        # the solve's flops only (the evaluation is O(n), the solve O(n^3))
+        flops = iters * WM.lstsq_flops((pe.PE_REAL | L) if real else L, n, n)
+        desc = (f"{iters} Gauss-Newton iterations, {'real quad' if real else 'complex double'} double, "
+                f"Chandrasekhar H-equation n = {n} (c = 33/64) from H = 1")
+        out = line(desc, L, iters / dt, iters, 1, dt,
+                   {"name": f"newton_table{table}_n{n}", "kernel_ms": kms,
+                    "F_norm_per_iteration": norms, "step_inf_norm_per_iteration": steps,
+                    "solve_flops_per_iteration": flops / iters,
+                    f"paper_table{table}_gpu_s_context": ref[n]}, alu_roofline(flops, kms), None)
+        out["metric"] = "Gauss-Newton iterations/s (context)"
+        out["unit"] = "iterations/s"
+        if real:
+            out["dtype"] = "f64 (quad-double real)"
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -579,7 +644,8 @@ def main():
                     help="dd_batch4096 (default, the reported line); d_n32, dd_n256, qd_n1024, "
                          "dd_adjoint_1024x512, d_product_65024x1024, cyclic_d_n512, cyclic_dd_n512, "
                          "terms_d_product_65024x1024, newton_dd_n256, newton_batch4096 and "
-                         "newton_rqd_chandrasekhar1016 print the same kind of line for context")
+                         "newton_rqd_chandrasekhar1016 print the same kind of line for context; newton_table3 "
+                         "and newton_table4 run the paper's Newton experiments on the H-equation")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path (rows of F and J would shard "
@@ -604,6 +670,10 @@ def main():
         return bench_terms_product(args)
     if args.workload == "newton_rqd_chandrasekhar1016":
         return bench_real_qd_chandrasekhar(args)
+    if args.workload == "newton_table3":
+        return bench_newton_tables(args, 3)
+    if args.workload == "newton_table4":
+        return bench_newton_tables(args, 4)
     if args.workload == "dd_adjoint_1024x512":
         return bench_adjoint(args)
     if args.workload == "d_product_65024x1024":

@@ -94,12 +94,13 @@ const char* pe_last_error(void);
  *   stream    stream used for the uploads (the call synchronises it).
  * Monomials with no occurrence (constants) and polynomials with no monomial
  * are allowed; duplicate monomials are kept as given (never merged).
- * Size limits (PE_EUNSUPPORTED beyond them): n <= 2048 variables; a
+ * Size limits (PE_EUNSUPPORTED beyond them): n <= 65535 variables (rows of
+ * J wider than 2048 columns are evaluated in tiles of 2048 columns, one
+ * workgroup each; the adjoint and batches take at most 2048 variables); a
  * monomial spans at most one wavefront of 64 lanes, so it has at most
  * 64 * segment variables: 1024 in double and double double (segment 16),
  * 512 in quad double (segment 8); systems with monomials that wide get that
- * segment by default; at most 2^31 monomials and 2^32 occurrences.  (n > 65535 and monomials over 1024 variables are
- * rejected by the validation itself.)
+ * segment by default; at most 2^31 monomials and 2^32 occurrences.
  * Returns PE_EINVAL for malformed input (out-of-range index, exponent < 1,
  * duplicate variable in a monomial, non-monotone offsets), PE_EUNSUPPORTED
  * for the size limits above, PE_ENOMEM or PE_EDEVICE on allocation/copy

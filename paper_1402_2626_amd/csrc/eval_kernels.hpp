@@ -58,7 +58,15 @@ struct SysView {
                               // point takes row row_order[b]), or null: row b
   const uint32_t* occ_orig;   // like occ: input index of each record's occurrence
   const uint32_t* mon_orig;   // [M] input index of each packed monomial
+  int col_tiles;  // tiles of kTileCols columns of a row of J (1 when n <= kTileCols)
+  int col0;       // first column of the tile a workgroup owns (0 on the host)
 };
+
+// A row of J wider than kTileCols columns is evaluated by one workgroup per
+// tile of kTileCols columns: every tile's workgroup runs the row's monomial
+// phase (F and the partials), and its owner lanes add the slots of their
+// tile's columns only (256 lanes x at most 8 columns each).
+constexpr int kTileCols = 2048;
 
 // destinations of the TERMS mode at one point: the value of input monomial t
 // at V[t] (planes v_plane apart), the partial derivative of input occurrence
@@ -276,7 +284,7 @@ __device__ __forceinline__ void load_chunk_of(const SysView& S, const ChunkDesc&
   const ChunkDesc& cd = cl.cd;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    const int c = lt + cc * kSub;
+    const int c = S.col0 + lt + cc * kSub;
     const bool use = MODE != MODE_FONLY && MODE != MODE_TERMS && act && c < S.n;
     cl.cb[cc] = use ? int(S.colptr[cd.colptr_base + c]) : 0;
     cl.ce[cc] = use ? int(S.colptr[cd.colptr_base + c + 1]) : 0;
@@ -660,11 +668,13 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
                                           double* scratch, const double* fpart) {
   const int sg = sub_group();
   const int lt = int(threadIdx.x) - sg * kSub;
+  // columns of this workgroup's tile: S.col0 .. S.col0 + nt - 1
+  const int nt = min(S.n - S.col0, kTileCols);
   if (MODE == MODE_EVAL && G > 1 && sg > 0) {
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
-      if (c < S.n) lds_st(scratch + size_t(sg - 1) * width_of(L) * S.n, S.n, c, acc[cc]);
+      if (c < nt) lds_st(scratch + size_t(sg - 1) * width_of(L) * nt, nt, c, acc[cc]);
     }
   }
   __syncthreads();
@@ -674,17 +684,17 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           const int c = lt + cc * kSub;
-          if (c < S.n) acc[cc] = c_add(acc[cc], lds_ld<L>(scratch + size_t(o - 1) * width_of(L) * S.n, S.n, c));
+          if (c < nt) acc[cc] = c_add(acc[cc], lds_ld<L>(scratch + size_t(o - 1) * width_of(L) * nt, nt, c));
         }
       }
     }
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int c = lt + cc * kSub;
-      if (c < S.n) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, c, acc[cc]);
+      if (c < nt) store_planar(O.J + pt * O.j_pt + int64_t(p) * O.j_row, O.j_plane, S.col0 + c, acc[cc]);
     }
   }
-  if (int(threadIdx.x) == (4 * G - 1) * 64) {
+  if (int(threadIdx.x) == (4 * G - 1) * 64 && S.col0 == 0) {
     C<L> F = lds_ld<L>(fpart, kMaxWaves, 0);
     for (int o = 1; o < 4 * G; ++o) F = c_add(F, lds_ld<L>(fpart, kMaxWaves, o));
     if (O.f_sign < 0) F = c_neg(F);
@@ -694,17 +704,20 @@ __device__ __forceinline__ void write_row(const SysView& S, const OutView& O, in
 
 // ------------------------------------------------------------------ kernels
 
-// grid: P * N workgroups of G * 256 threads; block (pt, b) = (blockIdx.x / N,
-// blockIdx.x % N) evaluates row p = row_order[b] (p = b without an order) at
-// point pt
+// grid: P * N * col_tiles workgroups of G * 256 threads; block (pt, b, tile)
+// (blockIdx.x = (pt * N + b) * col_tiles + tile) evaluates row
+// p = row_order[b] (p = b without an order) at point pt, columns of J from
+// tile * kTileCols; F is written by tile 0
 template <int L, int SEG, int CPL, int G, int MODE>
 __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView O, const double* __restrict__ x,
                                                              int64_t x_pt) {
   static_assert(G <= kRowDesc, "the first chunk of every sub-group comes from the row-ordered descriptors");
   static_assert(4 * G <= kMaxWaves, "F partials region");
   extern __shared__ double lds[];
-  const int pt = blockIdx.x / S.N;
-  const int b = blockIdx.x - pt * S.N;
+  const int rb = blockIdx.x / S.col_tiles;
+  S.col0 = (blockIdx.x - rb * S.col_tiles) * kTileCols;
+  const int pt = rb / S.N;
+  const int b = rb - pt * S.N;
   const int p = S.row_order ? int(S.row_order[b]) : b;
   const double* xpt = x + pt * x_pt;
   double* tab = lds;

@@ -107,8 +107,12 @@ hipError_t launch_rows_t(const EvalShape& sh, int P, const double* x, const OutV
   auto kern = eval_rows_kernel<L, SEG, CPL, G, MODE>;
   hipError_t e = allow_lds(kern, sh.lds);
   if (e != hipSuccess) return e;
-  const int64_t blocks = int64_t(P) * sh.view.N;
-  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), sh.lds, st, sh.view, O, x,
+  // F alone and the terms need no column tiles (no owners): one workgroup
+  // per row-point
+  SysView view = sh.view;
+  if (MODE == MODE_TERMS || MODE == MODE_FONLY) view.col_tiles = 1;
+  const int64_t blocks = int64_t(P) * view.N * view.col_tiles;
+  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), sh.lds, st, view, O, x,
                      int64_t(width_of(L)) * sh.view.n);
   return hipGetLastError();
 }

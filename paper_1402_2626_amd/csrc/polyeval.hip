@@ -219,8 +219,8 @@ pe_status choose_plan(pe_system* sys, int seg, int force_G) {
   Plan pl;
   pl.seg = seg;
   pl.max_slots = std::max(H.max_slots_used, 1);
-  pl.cpl = cpl_bucket(H.n, kSub);
-  if (pl.cpl == 0) return fail(PE_EUNSUPPORTED, "more than 2048 variables is not supported");
+  // owner columns per lane for one tile of at most kTileCols columns
+  pl.cpl = cpl_bucket(std::min(H.n, kTileCols), kSub);
   const size_t limit = device_lds_limit();
   const int L = H.level;
   // lds_bytes<1> counts 2 doubles per number; the level's width is W
@@ -335,6 +335,8 @@ pe_status pack_and_upload(pe_system* sys, int seg, int force_G, hipStream_t hs) 
   V.tab_first = sys->plan.tab_first;
   V.tab_last = sys->plan.tab_last;
   V.max_slots = sys->plan.max_slots;
+  V.col_tiles = (P.n + kTileCols - 1) / kTileCols;
+  V.col0 = 0;
   pe_status e = PE_OK;
   if ((e = upload(sys, P.chunks, V.chunks, hs)) != PE_OK || (e = upload(sys, P.chunk_ptr, V.chunk_ptr, hs)) != PE_OK ||
       (e = upload(sys, P.rowdesc, V.rowdesc, hs)) != PE_OK ||
@@ -648,6 +650,7 @@ pe_status pe_eval_adjoint(const pe_system* sys, int32_t P, const double* x, cons
   if (P == 0) return PE_OK;
   if (!x || !v || !g) return fail(PE_EINVAL, "x, v or g is NULL");
   if (is_real(sys->code)) return fail(PE_EUNSUPPORTED, "the adjoint is implemented for complex systems");
+  if (sys->view.col_tiles > 1) return fail(PE_EUNSUPPORTED, "the adjoint supports at most 2048 variables");
   const int L = sys->level, n = sys->view.n, N = sys->view.N;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   if (N == 0) {
@@ -730,6 +733,7 @@ pe_status pe_eval_adjoint_static(const pe_system* sys, int32_t P, const double* 
   if (P == 0) return PE_OK;
   if (!x || !v || !g) return fail(PE_EINVAL, "x, v or g is NULL");
   if (is_real(sys->code)) return fail(PE_EUNSUPPORTED, "the adjoint is implemented for complex systems");
+  if (sys->view.col_tiles > 1) return fail(PE_EUNSUPPORTED, "the adjoint supports at most 2048 variables");
   const int L = sys->level, n = sys->view.n, N = sys->view.N;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   const size_t row_bytes = size_t(P) * 2 * L * n * sizeof(double);  // one partial row per point
@@ -1094,11 +1098,16 @@ pe_status pe_batch_create(pe_batch** out, int32_t S, const pe_system* const* sys
     }
   b->level = systems[0]->level;
   b->seg = systems[0]->plan.seg;
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < S; ++s) {
     if (is_real(systems[s]->code)) {
       delete b;
       return fail(PE_EUNSUPPORTED, "batches are implemented for complex systems");
     }
+    if (systems[s]->view.col_tiles > 1) {
+      delete b;
+      return fail(PE_EUNSUPPORTED, "batched systems have at most 2048 variables");
+    }
+  }
   b->device = systems[0]->device;
   for (int s = 0; s < S; ++s) {
     const pe_system* y = systems[s];

@@ -56,6 +56,37 @@ FLOPS = {
 }
 
 
+# Real level-L operations, counted the same way: a product (DD with FMA
+# two-product, QD order 0..2 partial products exact) and a sum (DD sloppy,
+# QD order by order).
+RFLOPS = {
+    1: dict(mul=1, add=1),
+    2: dict(mul=10, add=11),
+    4: dict(mul=96, add=85),
+}
+
+
+def lstsq_multiply_adds(N: int, n: int) -> int:
+    """Multiply-adds of one least-squares solve of an N x n system by modified
+    Gram-Schmidt on the augmented N x (n + 1) matrix (Sec. 3, Fig. 4) and back
+    substitution (eq. (4)): each pair of columns c < j takes N for the inner
+    product and N for the update, each column N for its squared norm, and the
+    back substitution n (n + 1) / 2."""
+    return N * n * (n + 1) + N * (n + 1) + n * (n + 1) // 2
+
+
+def lstsq_flops(level_code: int, N: int, n: int) -> float:
+    """FP64 flops of lstsq_multiply_adds at a level code (1, 2, 4 complex;
+    8 | L real): a complex multiply-add is a complex product plus a complex
+    sum, a real one a product plus a sum."""
+    L = level_code & 7
+    if level_code & 8:
+        f = RFLOPS[L]["mul"] + RFLOPS[L]["add"]
+    else:
+        f = FLOPS[L]["cmul"] + FLOPS[L]["cadd_F"]
+    return float(lstsq_multiply_adds(N, n)) * f
+
+
 def algorithmic_products(k: int, ell: int) -> int:
     """Complex products of one monomial by the method's own count."""
     if k <= 0:

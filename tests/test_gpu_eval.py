@@ -478,14 +478,13 @@ def test_cyclic_512_random_point(pe, L):
 
 
 @pytest.mark.parametrize("level, n, k, words", [
-    (2, 2049, 3, "2048 variables"),
-    (1, 2049, 3, "2048 variables"),
+    (2, 65536, 3, "65535"),
     (2, 1100, 1025, "more than 1024 variables"),
     (4, 600, 513, "too large for the segment"),
 ])
 def test_size_limits_are_reported(pe, level, n, k, words):
-    """The size limits of the header: more than 2048 variables, a monomial of
-    more than 1024 variables and a quad-double monomial of 513 are refused
+    """The size limits of the header: more than 65535 variables, a monomial
+    of more than 1024 variables and a quad-double monomial of 513 are refused
     with PE_EUNSUPPORTED through the C ABI, and nothing is created."""
     import ctypes
     sys_ = synth.random_system(5, level, n_vars=n, n_polys=2, m=2, k=k, exp_lo=1, exp_hi=2)
@@ -497,7 +496,7 @@ def test_size_limits_are_reported(pe, level, n, k, words):
     assert not h.value
     # the largest sizes within the limits load and evaluate
     kmax = {1: 1024, 2: 1024, 4: 512}[level]
-    ok = synth.random_system(6, level, n_vars=min(n, 2048), n_polys=1, m=1, k=min(k, kmax, min(n, 2048)),
+    ok = synth.random_system(6, level, n_vars=min(n, 4096), n_polys=1, m=1, k=min(k, kmax),
                              exp_lo=1, exp_hi=1)
     S = pe.System.from_sparse(ok)
     S.close()

@@ -80,3 +80,63 @@ def test_wide_monomials(pe, level, k, seg):
     eF, eJ = U.max_errors_entries(sys_, x[0], F, J, picks)
     tol = U.tolerance(sys_)
     assert eF <= tol and eJ <= tol, (eF, eJ, tol)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_wide_rows_in_column_tiles(pe, L):
+    """Rows of J wider than 2048 columns (n = 4500: three tiles of 2048
+    columns, one workgroup each): every row of F and J at two points against
+    the oracle, and F of the F-only evaluation (one workgroup per row, F from
+    the forward products) too; the adjoint and batches refuse the system."""
+    import torch
+    n = 4500
+    sys_ = synth.random_system((761, L), L, n_vars=n, n_polys=6, m=150, k=5, exp_lo=1, exp_hi=3)
+    x = synth.unit_circle_points(synth.rng_for((762, L)), 2, n, L)
+    S = pe.System.from_sparse(sys_)
+    xd = U.to_device(x)
+    F, J = S.eval(xd)
+    F2, _ = S.eval(xd, want_J=False)
+    torch.cuda.synchronize()
+    F, J, F2 = F.cpu().numpy(), J.cpu().numpy(), F2.cpu().numpy()
+    tol = U.tolerance(sys_)
+    for pt in range(2):
+        eF, eJ = U.max_errors_rows(sys_, x[pt], F[pt], J[pt], range(sys_.n_polys))
+        eF2, _ = U.max_errors_rows(sys_, x[pt], F2[pt], J[pt], range(sys_.n_polys))
+        U.flush(f"wide rows L={L} point {pt}: eF={eF:.2e} eJ={eJ:.2e} F-only {eF2:.2e} tol={tol:.1e}")
+        assert eF <= tol and eJ <= tol and eF2 <= tol, (pt, eF, eJ, eF2)
+    if L == 2:
+        v = torch.zeros((2, 2, L, sys_.n_polys), dtype=torch.float64, device="cuda")
+        with pytest.raises(pe.PolyevalError):
+            S.adjoint(xd, v)
+        with pytest.raises(pe.PolyevalError):
+            pe.Batch([S])
+    S.close()
+
+
+def test_newton_chandrasekhar_4096(pe):
+    """The largest case of the paper's Table 3: Chandrasekhar's H-equation at
+    n = 4096 in complex double double, six Gauss-Newton iterations from H = 1
+    (evaluation in column tiles, least squares by the column-parallel MGS):
+    the step sizes decrease quadratically to the level's floor and at the end
+    F is zero to the tolerance on sampled rows (oracle), H real and above 1."""
+    import torch
+    n, L = 4096, 2
+    sys_ = synth.chandrasekhar_system(n, L)
+    S = pe.System.from_sparse(sys_)
+    x = torch.zeros((1, 2, L, n), dtype=torch.float64, device="cuda")
+    x[0, 0, 0] = 1.0
+    ws = torch.empty((S.newton_workspace_bytes(1) + 7) // 8, dtype=torch.float64, device="cuda")
+    steps = []
+    for it in range(6):
+        _, r = S.newton_step(x, workspace=ws)
+        torch.cuda.synchronize()
+        steps.append(float(r.cpu().numpy()[0, 1]))
+        U.flush(f"chandrasekhar 4096 DD: step {it}: |dx| = {steps[-1]:.3e}")
+    S.close()
+    for a, b in zip(steps, steps[1:]):
+        assert b <= 1e4 * a * a + 1e-27, steps
+    xe = x.cpu().numpy()[0]
+    rows = [0, 1, 2047, 4094, 4095]
+    eF = U.max_value_ratio(U.row_subsystem(sys_, rows), xe, range(len(rows)))
+    assert eF <= U.tolerance(sys_) * 8, eF
+    assert np.all(xe[0, 0] > 1.0) and np.all(np.abs(xe[1, 0]) <= 1e-25)

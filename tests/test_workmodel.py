@@ -13,6 +13,7 @@ product count of the work model.
 """
 from collections import Counter
 
+import numpy as np
 import pytest
 
 from paper_1402_2626_amd import workmodel as W
@@ -174,3 +175,80 @@ def test_survey_count_bounds_the_schedule():
     for k in range(1, 40):
         for ell in (0, 1, k // 2, k):
             assert W.algorithmic_products(k, ell) >= W.executed_products(k, ell)
+
+
+class _Counted:
+    """A number that counts the products made with it (a sum follows each
+    product in a multiply-add)."""
+    products = 0
+
+    def __init__(self, v):
+        self.v = v
+
+    def __mul__(self, o):
+        _Counted.products += 1
+        return _Counted(self.v * (o.v if isinstance(o, _Counted) else o))
+
+    __rmul__ = __mul__
+
+    def __add__(self, o):
+        return _Counted(self.v + (o.v if isinstance(o, _Counted) else o))
+
+    __radd__ = __add__
+
+    def __sub__(self, o):
+        return _Counted(self.v - (o.v if isinstance(o, _Counted) else o))
+
+    def __truediv__(self, o):
+        return _Counted(self.v / (o.v if isinstance(o, _Counted) else o))
+
+
+@pytest.mark.parametrize("N, n", [(1, 1), (3, 2), (7, 4), (12, 9)])
+def test_lstsq_count_matches_a_counted_solve(N, n):
+    """Modified Gram-Schmidt on the N x (n + 1) augmented matrix with
+    unnormalised pivots (Sec. 3, Fig. 4) and back substitution, written as
+    plain loops over counting numbers: the products made equal the work
+    model's multiply-adds (with the back substitution's n divisions), and
+    the solution is the least-squares one."""
+    rng = synth.rng_for((7, N, n))
+    A = rng.standard_normal((N, n + 1)) + 3.0 * np.eye(N, n + 1)
+    W_ = [[_Counted(float(A[i, j])) for j in range(n + 1)] for i in range(N)]
+    _Counted.products = 0
+    nrm = []
+    R = [[None] * (n + 1) for _ in range(n + 1)]
+    for c in range(n + 1):
+        s = _Counted(0.0)
+        for i in range(N):
+            s = s + W_[i][c] * W_[i][c]
+        nrm.append(s)
+        for j in range(c + 1, n + 1):
+            d = _Counted(0.0)
+            for i in range(N):
+                d = d + W_[i][c] * W_[i][j]
+            R[c][j] = d
+            f = d / s
+            for i in range(N):
+                W_[i][j] = W_[i][j] - f * W_[i][c]
+    # back substitution on the unnormalised factors: x_j = (y_j - sum_{l > j} r_jl x_l) / |a_j|^2
+    x = [None] * n
+    for j in range(n - 1, -1, -1):
+        t = R[j][n]
+        for l in range(j + 1, n):
+            t = t - R[j][l] * x[l]
+        x[j] = t / nrm[j]
+    # the model counts the n divisions of the back substitution with its products
+    assert _Counted.products + n == W.lstsq_multiply_adds(N, n)
+    if N >= n:
+        want = np.linalg.lstsq(A[:, :n], A[:, n], rcond=None)[0]
+        assert np.allclose([v.v for v in x], want, rtol=1e-9, atol=1e-9)
+
+
+def test_real_and_complex_solve_flops():
+    """Complex flops are (cmul + cadd_F) per multiply-add, real ones
+    (mul + add); a complex multiply-add costs more than twice a real one at
+    every level."""
+    for L in (1, 2, 4):
+        m = W.lstsq_multiply_adds(100, 50)
+        assert W.lstsq_flops(L, 100, 50) == m * (W.FLOPS[L]["cmul"] + W.FLOPS[L]["cadd_F"])
+        assert W.lstsq_flops(8 | L, 100, 50) == m * (W.RFLOPS[L]["mul"] + W.RFLOPS[L]["add"])
+        assert W.lstsq_flops(L, 100, 50) > 2 * W.lstsq_flops(8 | L, 100, 50)
