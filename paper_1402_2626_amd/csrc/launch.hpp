@@ -348,6 +348,7 @@ hipError_t ls_sweep_for(const LsView& V, int P, hipStream_t st) {
     if (N <= 512) return ls_sweep<L, 256, 2>(V, P, st);
     if (N <= 1024) return ls_sweep<L, 256, 4>(V, P, st);
     if (N <= 2048) return ls_sweep<L, 256, 8>(V, P, st);
+    if (N <= 3072) return ls_sweep<L, 384, 8>(V, P, st);
     if (N <= 4096) return ls_sweep<L, 512, 8>(V, P, st);
   } else {
     if (N <= 256) return ls_sweep<L, 256, 1>(V, P, st);

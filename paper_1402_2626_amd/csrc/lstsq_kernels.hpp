@@ -45,7 +45,9 @@ namespace pe {
 //   W     [P][2L][n + 1][N]   column-major working copy (column c plane-major)
 //   R     [P][2L][n + 1][n]   R column-major: entry (i, j) at [j][i]; column n
 //                             is y = Q^H b
-//   nrm   [P][n + 1][L]       squared norms of the pivot columns
+//   nrm   [P][n + 1][4][L]    per pivot column: its squared norm s, sqrt(s),
+//                             1 / sqrt(s) and 1 / s (computed once by the
+//                             column's owner, read by every later column)
 //   rmax  [P][n + 1]          largest |r_cc| up to and including column c
 //   yw    [P][2L][n]          right-hand side of the back substitution
 //   flag  [P]                 int: 1 when a pivot was numerically zero
@@ -65,7 +67,7 @@ inline LsLayout ls_layout(int L, int N, int n, int P) {
   lo.P = P;
   lo.w_pt = int64_t(width_of(L)) * (n + 1) * N;
   lo.r_pt = int64_t(width_of(L)) * (n + 1) * n;
-  lo.nrm_pt = int64_t(n + 1) * limbs_of(L);
+  lo.nrm_pt = int64_t(n + 1) * 4 * limbs_of(L);
   lo.rmax_pt = n + 1;
   lo.y_pt = int64_t(width_of(L)) * n;
   size_t off = 0;
@@ -162,8 +164,11 @@ __global__ __launch_bounds__(256) void ls_copy_in_kernel(LsView V, const double*
 // result in every thread: XOR butterfly in each wavefront (the additions are
 // commutative, so both lanes of a pair compute the same sum), then the
 // wavefront sums added in order by every thread.  `red` holds T / 64 values
-// of type V; two barriers.
-template <int T, typename V, typename Add, typename Shfl>
+// of type V.  With REUSE the buffer is free again on return (two barriers);
+// without, one barrier, and the caller alternates between two buffers: a
+// thread writes buffer b again only after the barrier of the sum in between,
+// which every thread reaches after its reads of b.
+template <int T, bool REUSE = true, typename V, typename Add, typename Shfl>
 __device__ __forceinline__ V wg_sum(V v, V* red, Add add, Shfl shfl) {
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) v = add(v, shfl(v, m));
@@ -173,7 +178,7 @@ __device__ __forceinline__ V wg_sum(V v, V* red, Add add, Shfl shfl) {
   V s = red[0];
 #pragma unroll
   for (int i = 1; i < T / 64; ++i) s = add(s, red[i]);
-  __syncthreads();
+  if (REUSE) __syncthreads();
   return s;
 }
 
@@ -196,7 +201,7 @@ template <int L, int T, int EPT>
 __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, int j0, int j1) {
   using RL = R<limbs_of(L)>;
   constexpr int NL = limbs_of(L);
-  __shared__ C<L> red_c[T / 64];
+  __shared__ C<L> red_c[2][T / 64];
   __shared__ RL red_r[T / 64];
   const int ncol = V.n + 1;
   const int cols = j1 - j0;
@@ -219,32 +224,67 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
   auto radd = [](const RL& x, const RL& y) { return r_add(x, y); };
   auto rshf = [](const RL& x, int m) { return shfl_xor_r(x, m); };
   const double thresh = double(V.n) * ls_unit<L>();
-  for (int c = k0; c < cend; ++c) {
-    RL nc;
+  // the pivot's rows: kept in registers for the update in double and
+  // double double; quad double loads them again (an L2 hit) so that the
+  // column alone fills the registers.  Up to 2 rows per thread the next
+  // pivot's rows are loaded while the current one is applied.
+  constexpr bool kKeep = width_of(L) <= 4;
+  constexpr bool kPre = kKeep && EPT <= 2;
+  const double* pvb = V.nrm + p * V.nrm_pt;
+  auto load_q = [&](int c, C<L>* q) {
 #pragma unroll
-    for (int l = 0; l < NL; ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * NL + l];
-    const RL rcc = r_sqrt(nc);
+    for (int e = 0; e < EPT; ++e) {
+      const int i = e * T + tid;
+      q[e] = i < N ? load_planar<L>(Wp + int64_t(c) * N, plane, i) : c_zero<L>();
+    }
+  };
+  C<L> qn[kPre ? EPT : 1];
+  if (kPre && k0 < cend) load_q(k0, qn);
+  for (int c = k0; c < cend; ++c) {
+    const double* pv = pvb + int64_t(c) * 4 * NL;
+    RL rcc, inv_r, inv_n;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      rcc.x[l] = pv[NL + l];
+      inv_r.x[l] = pv[2 * NL + l];
+      inv_n.x[l] = pv[3 * NL + l];
+    }
     const double rmax = V.rmax[p * V.rmax_pt + c];
     if (!(rcc.x[0] > thresh * rmax)) {
       if (j == c + 1 && tid == 0) V.flag[p] = 1;
       return;  // uniform: every thread read the same values
     }
-    // the pivot's rows: kept in registers for the update in double and
-    // double double; quad double loads them again (an L2 hit) so that the
-    // column alone fills the registers
-    constexpr bool kKeep = width_of(L) <= 4;
     C<L> q[kKeep ? EPT : 1];
-    C<L> dot = c_zero<L>();
+    if constexpr (kPre) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) q[e] = qn[e];
+      if (c + 1 < cend) load_q(c + 1, qn);
+    }
+    // the thread's rows in NA independent partial sums (a dependent chain
+    // of EPT additions would leave the SIMD waiting on each), added
+    // pairwise at the end
+    constexpr int NA = EPT < 4 ? EPT : 4;
+    C<L> part[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) part[k] = c_zero<L>();
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int i = e * T + tid;
-      const C<L> qe = i < N ? load_planar<L>(Wp + int64_t(c) * N, plane, i) : c_zero<L>();
-      if constexpr (kKeep) q[e] = qe;
-      dot = c_add(dot, c_mul(c_conj(qe), a[e]));
+      C<L> qe;
+      if constexpr (kPre) {
+        qe = q[e];
+      } else {
+        const int i = e * T + tid;
+        qe = i < N ? load_planar<L>(Wp + int64_t(c) * N, plane, i) : c_zero<L>();
+        if constexpr (kKeep) q[e] = qe;
+      }
+      part[e % NA] = c_add(part[e % NA], c_mul(c_conj(qe), a[e]));
     }
-    dot = wg_sum<T>(dot, red_c, cadd, cshf);
-    const RL inv_r = r_recip(rcc);
-    const RL inv_n = r_recip(nc);
+#pragma unroll
+    for (int h = 1; h < NA; h <<= 1) {
+#pragma unroll
+      for (int k = 0; k + h < NA; k += 2 * h) part[k] = c_add(part[k], part[k + h]);
+    }
+    const C<L> dot = wg_sum<T, false>(part[0], red_c[c & 1], cadd, cshf);
     double* Rp = V.R + p * V.r_pt;
     const int64_t rplane = int64_t(ncol) * V.n;
     if (tid == 0) {
@@ -276,11 +316,19 @@ __global__ __launch_bounds__(T) void ls_apply_kernel(LsView V, int k0, int k1, i
     for (int e = 0; e < EPT; ++e) s = r_add(s, c_norm2(a[e]));
     s = wg_sum<T>(s, red_r, radd, rshf);
     if (tid == 0) {
+      const RL r = r_sqrt(s);
+      const RL ir = r_recip(r);
+      const RL is = r_recip(s);
+      double* pv = V.nrm + p * V.nrm_pt + int64_t(j) * 4 * NL;
 #pragma unroll
-      for (int l = 0; l < NL; ++l) V.nrm[p * V.nrm_pt + int64_t(j) * NL + l] = s.x[l];
-      const double r = r_sqrt(s).x[0];
+      for (int l = 0; l < NL; ++l) {
+        pv[l] = s.x[l];
+        pv[NL + l] = r.x[l];
+        pv[2 * NL + l] = ir.x[l];
+        pv[3 * NL + l] = is.x[l];
+      }
       const double prev = j > 0 ? V.rmax[p * V.rmax_pt + j - 1] : 0.0;
-      V.rmax[p * V.rmax_pt + j] = fmax(prev, r);
+      V.rmax[p * V.rmax_pt + j] = fmax(prev, r.x[0]);
     }
   }
 }
@@ -302,10 +350,17 @@ __global__ void ls_init_y_kernel(LsView V) {
 
 // Solve the diagonal block [s, e) of R x = y: x_i = y_i / r_ii from the
 // bottom, each solved value subtracted from the block's rows above it.  The
-// solution overwrites y[s, e).  Grid P, kBs threads.
+// solution overwrites y[s, e).  The diagonal r_jj is the norm of pivot column
+// j, whose reciprocal the sweep stored; the block's reciprocals are staged in
+// LDS and each thread loads its entry of the next column of R while the
+// current one is applied, so the serial loop waits on no global load.  Grid
+// P, kBs threads.
 template <int L>
 __global__ __launch_bounds__(kBs) void ls_backsub_diag_kernel(LsView V, int s, int e) {
+  using RL = R<limbs_of(L)>;
+  constexpr int NL = limbs_of(L);
   __shared__ C<L> ysh[kBs];
+  __shared__ RL dinv[kBs];
   __shared__ C<L> xj;
   const int p = blockIdx.x;
   if (V.flag[p]) return;
@@ -313,20 +368,29 @@ __global__ __launch_bounds__(kBs) void ls_backsub_diag_kernel(LsView V, int s, i
   const int64_t rplane = int64_t(V.n + 1) * V.n;
   const double* Rp = V.R + p * V.r_pt;
   double* yp = V.y + p * V.y_pt;
-  if (s + tid < e) ysh[tid] = load_planar<L>(yp, V.n, s + tid);
+  const int i = s + tid;
+  if (i < e) {
+    ysh[tid] = load_planar<L>(yp, V.n, i);
+    const double* pv = V.nrm + p * V.nrm_pt + int64_t(i) * 4 * NL + 2 * NL;
+    RL d;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) d.x[l] = pv[l];
+    dinv[tid] = d;
+  }
+  C<L> rcol = i < e - 1 ? load_planar<L>(Rp + int64_t(e - 1) * V.n, rplane, i) : c_zero<L>();
   __syncthreads();
   for (int j = e - 1; j >= s; --j) {
     if (tid == 0) {
-      const R<limbs_of(L)> rjj = load_planar<L>(Rp + int64_t(j) * V.n, rplane, j).re;
-      xj = c_mul_r(ysh[j - s], r_recip(rjj));
+      xj = c_mul_r(ysh[j - s], dinv[j - s]);
       ysh[j - s] = xj;
     }
     __syncthreads();
-    const int i = s + tid;
-    if (i < j) ysh[tid] = c_sub(ysh[tid], c_mul(load_planar<L>(Rp + int64_t(j) * V.n, rplane, i), xj));
+    const C<L> rnext = (j > s && i < j - 1) ? load_planar<L>(Rp + int64_t(j - 1) * V.n, rplane, i) : c_zero<L>();
+    if (i < j) ysh[tid] = c_sub(ysh[tid], c_mul(rcol, xj));
+    rcol = rnext;
     __syncthreads();
   }
-  if (s + tid < e) store_planar(yp, V.n, s + tid, ysh[tid]);
+  if (i < e) store_planar(yp, V.n, i, ysh[tid]);
 }
 
 // y[0, s) -= R[0:s, s:e] x[s:e] (x[s:e] already in y[s:e]), one row per
@@ -417,11 +481,12 @@ __global__ void ls_export_kernel(LsView V, double* __restrict__ Rout, double* __
   }
   if (Qout && idx < int64_t(V.N) * V.n) {
     const int i = int(idx / V.n), c = int(idx - int64_t(i) * V.n);
-    R<limbs_of(L)> nc;
+    constexpr int NL = limbs_of(L);
+    R<NL> ir;
 #pragma unroll
-    for (int l = 0; l < limbs_of(L); ++l) nc.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * limbs_of(L) + l];
+    for (int l = 0; l < NL; ++l) ir.x[l] = V.nrm[p * V.nrm_pt + int64_t(c) * 4 * NL + 2 * NL + l];
     const int64_t plane = int64_t(ncol) * V.N;
-    const C<L> q = c_mul_r(load_planar<L>(V.W + p * V.w_pt + int64_t(c) * V.N, plane, i), r_recip(r_sqrt(nc)));
+    const C<L> q = c_mul_r(load_planar<L>(V.W + p * V.w_pt + int64_t(c) * V.N, plane, i), ir);
     store_planar(Qout + p * (int64_t(width_of(L)) * V.N * V.n), int64_t(V.N) * V.n, idx, q);
   }
 }
