@@ -112,14 +112,16 @@ def test_lstsq_matches_oracle(pe, L):
         assert wqr <= 64 * N and wqq <= 64 * N, (wqr, wqq)
 
 
-def test_lstsq_large_double_double(pe):
-    """N = 1100 rows, n = 1000 unknowns in double double (the 256 x 8 sweep):
-    sampled entries of A - QR and Q^H Q - I exactly, and x against numpy's
-    least squares on the leading limbs (float64 accuracy)."""
+@pytest.mark.parametrize("N, n", [(1100, 1000), (2600, 400)])
+def test_lstsq_large_double_double(pe, N, n):
+    """N = 1100 rows, n = 1000 unknowns in double double (the sweep of 256
+    threads x 8 rows) and N = 2600, n = 400 (384 threads x 8 rows): sampled
+    entries of A - QR and Q^H Q - I exactly, and x against numpy's least
+    squares on the leading limbs (float64 accuracy)."""
     import torch
-    L, N, n = 2, 1100, 1000
-    Ab = _random_Ab(811, L, 1, N, n)
-    U.flush("lstsq 1100 x 1000 DD: solving")
+    L = 2
+    Ab = _random_Ab((811, N), L, 1, N, n)
+    U.flush(f"lstsq {N} x {n} DD: solving")
     x, resid, R, Q = pe.lstsq(U.to_device(Ab), want_R=True, want_Q=True)
     torch.cuda.synchronize()
     x, R, Q = x.cpu().numpy()[0], R.cpu().numpy()[0], Q.cpu().numpy()[0]
@@ -129,13 +131,13 @@ def test_lstsq_large_double_double(pe):
     want = np.linalg.lstsq(A, b, rcond=None)[0]
     got = x[0, 0] + 1j * x[1, 0]
     rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    U.flush(f"lstsq 1100 x 1000 DD: kappa = {kappa:.0f}, |x - x_numpy| / |x| = {rel:.2e}")
+    U.flush(f"lstsq {N} x {n} DD: kappa = {kappa:.0f}, |x - x_numpy| / |x| = {rel:.2e}")
     assert rel <= 1e3 * kappa * 2.0 ** -53
-    rng = synth.rng_for(812)
+    rng = synth.rng_for((812, N))
     pairs_qr = [(int(rng.integers(N)), int(rng.integers(n + 1))) for _ in range(24)] + [(N - 1, n), (0, 0)]
     pairs_qq = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(16)] + [(n - 1, n - 1), (0, n - 1)]
     wqr, wqq = _check_factors(Ab[0], R, Q, L, pairs_qr, pairs_qq, kappa)
-    U.flush(f"lstsq 1100 x 1000 DD: A - QR {wqr:.1f} u, Q^H Q - I {wqq:.2e} u kappa")
+    U.flush(f"lstsq {N} x {n} DD: A - QR {wqr:.1f} u, Q^H Q - I {wqq:.2e} u kappa")
     assert wqr <= 64 * N and wqq <= 64 * N, (wqr, wqq)
 
 

@@ -126,11 +126,12 @@ def test_real_terms_match_oracle(pe, L):
                 assert O.rel_error(G[pt, 0, :, o0 + r], G[pt, 1, :, o0 + r], gr, sg) <= tol
 
 
-@pytest.mark.parametrize("L, n", [(4, 64), (4, 256), (2, 1024)])
+@pytest.mark.parametrize("L, n", [(4, 64), (4, 256), (2, 1024), (4, 2600)])
 def test_real_newton_chandrasekhar(pe, L, n):
     """Chandrasekhar's H-equation (Sec. 5.2, c = 33/64) in real quad double
     (the setting of Table 4; n = 64 on the one-workgroup solve, n = 256 on
-    the column-parallel one) and real double double at n = 1024, from H = 1:
+    the column-parallel one, n = 2600 on its 384-thread shape) and real
+    double double at n = 1024, from H = 1:
     at n = 64 the first step equals the oracle's Gauss-Newton step
     (Householder at 600 bits) to the level's accuracy, the iterates converge quadratically to the
     level's floor, and at the end F is zero to the tolerance on sampled rows
