@@ -439,6 +439,17 @@ def bench_newton_single(args):
         xd.copy_(xs)  # every timed step starts from the same point
         S.newton_step(xd, workspace=ws, resid=resid, stream=st)
     dt, ms = _time_steps(step, K, Wm, st)
+    # the same step captured once in a HIP graph and replayed (x is reset by
+    # a captured copy): what remains of the per-launch cost
+    gs = torch.cuda.Stream()
+    S.newton_step(xd.clone(), workspace=ws, resid=resid, stream=gs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=gs):
+        xd.copy_(xs)
+        S.newton_step(xd, workspace=ws, resid=resid, stream=gs)
+    torch.cuda.synchronize()
+    _, ms_graph = _time_steps(g.replay, K, Wm, torch.cuda.current_stream())
     F = torch.empty((1, 2, 2, 256), dtype=torch.float64, device="cuda")
     J = torch.empty((1, 2, 2, 256, 256), dtype=torch.float64, device="cuda")
     _, ms_eval = _time_steps(lambda: S.eval(xd, out=(F, J), stream=st), K, Wm, st)
@@ -448,7 +459,7 @@ def bench_newton_single(args):
     cmadd = WM.lstsq_multiply_adds(n, n)
     out = line("Gauss-Newton step, complex double-double, 256 x 256 system with a planted root (evaluation, "
                "least squares by modified Gram-Schmidt, update)", 2, sys_.n_monomials * K / dt, K, Wm, dt,
-               {"name": "newton_dd_n256", "kernel_ms": ms, "eval_ms": ms_eval,
+               {"name": "newton_dd_n256", "kernel_ms": ms, "graph_replay_ms": ms_graph, "eval_ms": ms_eval,
                 "solve_complex_mult_adds": cmadd}, None, None)
     out["metric"] = "Gauss-Newton steps/s (context)"
     out["value"] = K / dt

@@ -154,7 +154,9 @@ pe_status pe_system_set_shape(pe_system* sys, int32_t segment, int32_t chunks_pe
  *      monomial touches are written as 0); J == NULL evaluates F only.
  * Summation order is fixed, so results are bitwise reproducible run to run.
  * Enqueues only kernels (no allocation, no host synchronisation); it may be
- * captured in a HIP graph.  PE_EINVAL for NULL x/F with P > 0 or P < 0. */
+ * captured in a HIP graph.  PE_EINVAL for NULL x/F with P > 0 or P < 0;
+ * PE_EUNSUPPORTED when P * N * (column tiles of J: ceil(n / 2048), or 1 when
+ * J == NULL) exceeds 2^31 - 1 (one workgroup each). */
 pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, double* J,
                   void* stream);
 

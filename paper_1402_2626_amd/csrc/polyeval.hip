@@ -560,7 +560,9 @@ pe_status pe_eval(const pe_system* sys, int32_t P, const double* x, double* F, d
   if (P < 0) return fail(PE_EINVAL, "P must be nonnegative");
   if (P == 0 || sys->view.N == 0) return PE_OK;
   if (!x || !F) return fail(PE_EINVAL, "x or F is NULL");
-  if (int64_t(P) * sys->view.N > 0x7fffffffLL) return fail(PE_EUNSUPPORTED, "P * N too large");
+  // one workgroup per (point, row, column tile); F alone needs no tiles
+  if (int64_t(P) * sys->view.N * (J ? sys->view.col_tiles : 1) > 0x7fffffffLL)
+    return fail(PE_EUNSUPPORTED, "P * N (times the column tiles of J) too large");
   const int W = width_of(sys->code), n = sys->view.n, N = sys->view.N;
   OutView O;
   O.J = J;
@@ -830,6 +832,8 @@ pe_status newton_check(const pe_system* sys, int P) {
   if (newton_column_parallel(sys) && N > kLsMaxRows)
     return fail(PE_EUNSUPPORTED, "the least-squares solve supports at most 4096 polynomials");
   if (P > 65535) return fail(PE_EUNSUPPORTED, "at most 65535 points per call");
+  if (int64_t(P) * N * sys->view.col_tiles > 0x7fffffffLL)
+    return fail(PE_EUNSUPPORTED, "P * N (times the column tiles of J) too large");
   return PE_OK;
 }
 

@@ -500,3 +500,21 @@ def test_size_limits_are_reported(pe, level, n, k, words):
                              exp_lo=1, exp_hi=1)
     S = pe.System.from_sparse(ok)
     S.close()
+
+
+def test_grid_limit_counts_column_tiles(pe):
+    """One workgroup per (point, row, column tile) must stay below 2^31:
+    with n = 4500 (three tiles of J) and N = 2, P = 400,000,000 points pass
+    the P * N test alone but not with the tiles, so pe_eval refuses them
+    before any launch (the buffers are never touched)."""
+    import ctypes
+    import torch
+    sys_ = synth.random_system(7, 2, n_vars=4500, n_polys=2, m=3, k=3, exp_lo=1, exp_hi=2)
+    S = pe.System.from_sparse(sys_)
+    big = 400_000_000
+    buf = torch.zeros(8, dtype=torch.float64, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    st = pe._lib.pe_eval(S.handle, big, p, p, p, None)
+    assert st == pe.PE_EUNSUPPORTED, st
+    assert "column tiles" in pe._lib.pe_last_error().decode()
+    S.close()
