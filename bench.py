@@ -525,14 +525,15 @@ def bench_terms_product(args):
     K = min(args.steps, 50)
     Wm = min(args.warmup, 5)
     dt, ms = _time_steps(lambda: S.eval_terms(xd, out=(V, G), stream=st), K, Wm, st)
-    nbytes = W.bytes_per_point(sys_, want_J=True, chunks=sys_.n_polys)
+    nbytes = W.terms_bytes_per_point(sys_)
     gbs = nbytes / (ms * 1e-3) / 1e9
+    counters = load_counters("terms_d_product_65024x1024")
     out = line("value and gradient of each of 65,024 products of 1,024 variables (the paper's Table 1), "
                "complex double, per-monomial output", 1, sys_.n_monomials * K / dt, K, Wm, dt,
                {"name": "terms_d_product_65024x1024", "kernel_ms": ms, "algorithmic_bytes": nbytes,
                 "paper_table1_ms_context": 9.10},
                {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                "traffic": None}, None)
+                "traffic": counter_traffic(counters)}, None)
     S.close()
     print(json.dumps(out), flush=True)
 

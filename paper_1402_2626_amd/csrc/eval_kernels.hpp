@@ -611,17 +611,16 @@ template <int L, int SEG, int CPL, int G, int MODE>
 __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, uint32_t ch1,
                                                const double* __restrict__ xpt, const double* __restrict__ vpt,
                                                const double* tab, double* contrib_base, C<L> (&acc)[CPL],
-                                               double* fpart, ChunkLoads<L, SEG, CPL>& cl,
-                                               const TermsOut& to = TermsOut{}) {
+                                               double* fpart, ChunkLoads<L, SEG, CPL>& cl) {
   const int sg = sub_group();
   const int lt = int(threadIdx.x) - sg * kSub;
   double* contrib = contrib_base + size_t(sg) * S.max_slots * width_of(L);
   C<L> facc = c_zero<L>();
   if (MODE != MODE_ADJ && fpart && ch0 >= ch1) store_wave_f(facc, fpart);
   for (uint32_t base = ch0; base < ch1; base += G) {
-    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib, facc, to);
+    chunk_monomials<L, SEG, CPL, MODE>(S, cl, lt, xpt, tab, contrib, facc);
     if (MODE != MODE_ADJ && fpart && base + G >= ch1) store_wave_f(facc, fpart);
-    if (MODE == MODE_FONLY || MODE == MODE_TERMS) {
+    if (MODE == MODE_FONLY) {
       if (base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
       continue;
     }
@@ -737,18 +736,46 @@ __global__ __launch_bounds__(G * kSub) void eval_rows_kernel(SysView S, OutView 
   C<L> acc[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) acc[cc] = c_zero<L>();
-  if constexpr (MODE == MODE_TERMS) {
-    // values and partials go straight to their input positions: O.F and
-    // O.J hold the V and G arrays
-    TermsOut to;
-    to.V = O.F + pt * O.f_pt;
-    to.v_plane = O.f_plane;
-    to.G = O.J + pt * O.j_pt;
-    to.g_plane = O.j_plane;
-    process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, nullptr, cl, to);
-  } else {
-    process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
-    write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+  process_chunks<L, SEG, CPL, G, MODE>(S, ch0, ch1, xpt, nullptr, tab, contrib, acc, fpart, cl);
+  write_row<L, CPL, G, MODE>(S, O, pt, p, acc, contrib, fpart);
+}
+
+// Per-monomial output (values and partials written to their input
+// positions; no slots, no owners, no row sums): the four wavefronts of a
+// workgroup take chunks of any row one after another, each chunk in slices
+// of 64 lanes (the monomials of a chunk are aligned groups of s lanes, s a
+// power of two <= 64, so a slice holds whole monomials), and slice j of a
+// chunk runs exactly as lanes 64 j .. 64 j + 63 of a chunk-processing
+// sub-group would.  There is no barrier after the power table, which each
+// workgroup builds once per point.  grid: P * wpp workgroups of 256
+// threads; workgroup b of point pt takes chunks 4 b + w, 4 b + w + 4 wpp, ...
+// (w its wavefront) of the nch chunks.
+template <int L, int SEG>
+__global__ __launch_bounds__(kSub) void terms_waves_kernel(SysView S, OutView O, const double* __restrict__ x,
+                                                           int64_t x_pt, int wpp, uint32_t nch) {
+  extern __shared__ double lds[];
+  const int pt = blockIdx.x / wpp;
+  const int b = blockIdx.x - pt * wpp;
+  const double* xpt = x + pt * x_pt;
+  double* tab = lds;
+  const C<L> x0 = table_first_x<L>(S, xpt);
+  build_power_table<L, kSub>(S, xpt, tab, x0);
+  __syncthreads();
+  TermsOut to;
+  to.V = O.F + pt * O.f_pt;
+  to.v_plane = O.f_plane;
+  to.G = O.J + pt * O.j_pt;
+  to.g_plane = O.j_plane;
+  const uint32_t w = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6));
+  const int lane = int(threadIdx.x) & 63;
+  for (uint32_t ch = uint32_t(b) * 4 + w; ch < nch; ch += uint32_t(wpp) * 4) {
+    const ChunkDesc cd = S.chunks[ch];
+    for (int j = 0; 64 * j < int(cd.width); ++j) {
+      ChunkLoads<L, SEG, 1> cl;
+      load_chunk_of<L, SEG, 1, MODE_TERMS>(S, cd, true, 64 * j + lane, nullptr, cl);
+      C<L> facc = c_zero<L>();
+      chunk_monomials<L, SEG, 1, MODE_TERMS>(S, cl, 64 * j + lane, xpt, tab, nullptr, facc, to);
+    }
   }
 }
 

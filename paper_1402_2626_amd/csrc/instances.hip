@@ -14,6 +14,7 @@ namespace pe {
 
 #if PE_KIND == 0
 template hipError_t launch_rows<PE_LEVEL>(const EvalShape&, int, const double*, const OutView&, int, hipStream_t);
+template hipError_t launch_terms<PE_LEVEL>(const EvalShape&, int, const double*, const OutView&, hipStream_t);
 #elif PE_KIND == 1
 template hipError_t launch_adjoint<PE_LEVEL>(const EvalShape&, int, const double*, const double*, int, int, double*,
                                              double*, hipStream_t);

@@ -48,6 +48,7 @@ struct EvalShape {
   int seg = 4, G = 1, cpl = 1;
   size_t lds = 0;   // dynamic LDS of a workgroup of G chunks
   size_t lds1 = 0;  // dynamic LDS of a one-chunk workgroup
+  int64_t n_chunks = 0;  // chunks of the system (per-monomial output)
 };
 
 // one persistent launch over the items of a batch class
@@ -64,6 +65,10 @@ struct BatchShape {
 
 template <int L>
 hipError_t launch_rows(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st);
+
+// per-monomial output (terms_waves_kernel)
+template <int L>
+hipError_t launch_terms(const EvalShape& sh, int P, const double* x, const OutView& O, hipStream_t st);
 template <int L>
 hipError_t launch_adjoint(const EvalShape& sh, int P, const double* x, const double* v, int NG, int gsize,
                           double* part, double* g, hipStream_t st);
@@ -107,10 +112,9 @@ hipError_t launch_rows_t(const EvalShape& sh, int P, const double* x, const OutV
   auto kern = eval_rows_kernel<L, SEG, CPL, G, MODE>;
   hipError_t e = allow_lds(kern, sh.lds);
   if (e != hipSuccess) return e;
-  // F alone and the terms need no column tiles (no owners): one workgroup
-  // per row-point
+  // F alone needs no column tiles (no owners): one workgroup per row-point
   SysView view = sh.view;
-  if (MODE == MODE_TERMS || MODE == MODE_FONLY) view.col_tiles = 1;
+  if (MODE == MODE_FONLY) view.col_tiles = 1;
   const int64_t blocks = int64_t(P) * view.N * view.col_tiles;
   hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(G * kSub), sh.lds, st, view, O, x,
                      int64_t(width_of(L)) * sh.view.n);
@@ -120,7 +124,6 @@ hipError_t launch_rows_t(const EvalShape& sh, int P, const double* x, const OutV
 template <int L, int SEG, int G>
 hipError_t rows_lsg(const EvalShape& sh, int P, const double* x, const OutView& O, int mode, hipStream_t st) {
   const int cpl = sh.cpl;
-  if (mode == MODE_TERMS) return launch_rows_t<L, SEG, 1, G, MODE_TERMS>(sh, P, x, O, st);
   if (mode == MODE_EVAL) {
     if (cpl == 1) return launch_rows_t<L, SEG, 1, G, MODE_EVAL>(sh, P, x, O, st);
     if (cpl == 2) return launch_rows_t<L, SEG, 2, G, MODE_EVAL>(sh, P, x, O, st);
@@ -140,6 +143,36 @@ hipError_t launch_rows(const EvalShape& sh, int P, const double* x, const OutVie
 #define PE_X(L_, S_, G_) \
   if constexpr (limbs_of(L) == L_) \
     if (sh.seg == S_ && sh.G == G_) return rows_lsg<L, S_, G_>(sh, P, x, O, mode, st);
+  PE_SHAPES(PE_X)
+#undef PE_X
+  return hipErrorInvalidValue;
+}
+
+template <int L, int SEG>
+hipError_t launch_terms_t(const EvalShape& sh, int P, const double* x, const OutView& O, hipStream_t st) {
+  auto kern = terms_waves_kernel<L, SEG>;
+  const SysView& V = sh.view;
+  const size_t lds = size_t(V.tab_last >= V.tab_first ? V.tab_last - V.tab_first + 1 : 0) * (V.n + 1) *
+                     width_of(L) * sizeof(double);
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  // about eight chunks per wavefront (the table is built once per
+  // workgroup), and at least 2048 workgroups in all when there are chunks
+  // enough
+  const int64_t quads = (sh.n_chunks + 3) / 4;
+  int64_t wpp = std::max<int64_t>((quads + 7) / 8, (2048 + P - 1) / P);
+  wpp = std::max<int64_t>(1, std::min<int64_t>(wpp, quads));
+  if (int64_t(P) * wpp > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * wpp)), dim3(kSub), lds, st, V, O, x,
+                     int64_t(width_of(L)) * V.n, int(wpp), uint32_t(sh.n_chunks));
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_terms(const EvalShape& sh, int P, const double* x, const OutView& O, hipStream_t st) {
+#define PE_X(L_, S_, G_) \
+  if constexpr (limbs_of(L) == L_ && G_ == 1) \
+    if (sh.seg == S_) return launch_terms_t<L, S_>(sh, P, x, O, st);
   PE_SHAPES(PE_X)
 #undef PE_X
   return hipErrorInvalidValue;

@@ -622,6 +622,7 @@ pe_status pe_eval_terms(const pe_system* sys, int32_t P, const double* x, double
   EvalShape sh = eval_shape(sys);
   sh.view.occ_orig = sys->d_occ_orig;
   sh.view.mon_orig = sys->d_mon_orig;
+  sh.n_chunks = int64_t(H.chunks.size());
   OutView O;
   O.F = V;
   O.f_plane = H.M;
@@ -633,13 +634,14 @@ pe_status pe_eval_terms(const pe_system* sys, int32_t P, const double* x, double
   O.j_pt = W * H.nnz;
   O.j_row = 0;
   hipError_t e = hipErrorInvalidValue;
+  if (sh.n_chunks == 0) return PE_OK;
   switch (sys->code) {
-    case 1: e = launch_rows<1>(sh, P, x, O, MODE_TERMS, hs); break;
-    case 2: e = launch_rows<2>(sh, P, x, O, MODE_TERMS, hs); break;
-    case 4: e = launch_rows<4>(sh, P, x, O, MODE_TERMS, hs); break;
-    case PE_REAL | 1: e = launch_rows<PE_REAL | 1>(sh, P, x, O, MODE_TERMS, hs); break;
-    case PE_REAL | 2: e = launch_rows<PE_REAL | 2>(sh, P, x, O, MODE_TERMS, hs); break;
-    case PE_REAL | 4: e = launch_rows<PE_REAL | 4>(sh, P, x, O, MODE_TERMS, hs); break;
+    case 1: e = launch_terms<1>(sh, P, x, O, hs); break;
+    case 2: e = launch_terms<2>(sh, P, x, O, hs); break;
+    case 4: e = launch_terms<4>(sh, P, x, O, hs); break;
+    case PE_REAL | 1: e = launch_terms<PE_REAL | 1>(sh, P, x, O, hs); break;
+    case PE_REAL | 2: e = launch_terms<PE_REAL | 2>(sh, P, x, O, hs); break;
+    case PE_REAL | 4: e = launch_terms<PE_REAL | 4>(sh, P, x, O, hs); break;
   }
   if (e != hipSuccess) return fail(PE_EDEVICE, std::string("terms launch: ") + hipGetErrorString(e));
   return PE_OK;

@@ -143,6 +143,15 @@ def executed_flops_per_point(sys_) -> float:
     return _flops(sys_.level, executed_counts(sys_))
 
 
+def terms_bytes_per_point(sys_) -> float:
+    """Bytes one per-monomial evaluation (values and partials written in
+    input order, nothing summed) must move at one point: the records (8 bytes
+    per occurrence), the coefficients and x read; each monomial's value and
+    each occurrence's partial derivative written (16L bytes each)."""
+    c16 = 16 * sys_.level
+    return 8.0 * sys_.nnz + 2.0 * c16 * sys_.n_monomials + c16 * sys_.n_vars + c16 * sys_.nnz
+
+
 def bytes_per_point(sys_, want_J: bool = True, chunks: int | None = None) -> float:
     L = sys_.level
     c16 = 16 * L

@@ -252,3 +252,15 @@ def test_real_and_complex_solve_flops():
         assert W.lstsq_flops(L, 100, 50) == m * (W.FLOPS[L]["cmul"] + W.FLOPS[L]["cadd_F"])
         assert W.lstsq_flops(8 | L, 100, 50) == m * (W.RFLOPS[L]["mul"] + W.RFLOPS[L]["add"])
         assert W.lstsq_flops(L, 100, 50) > 2 * W.lstsq_flops(8 | L, 100, 50)
+
+
+def test_terms_bytes_count_the_outputs_once():
+    """Per-monomial output moves each record once (8 bytes), reads the
+    coefficients and x, and writes one value per monomial and one partial per
+    occurrence (16L bytes each): for the Table-1 shape at L = 1 that is
+    8 nnz + 32 M + 16 n + 16 nnz."""
+    from paper_1402_2626_amd import synth
+    s = synth.product_system(5, 7, 1)
+    assert W.terms_bytes_per_point(s) == 8 * 35 + 32 * 5 + 16 * 7 + 16 * 35
+    s2 = synth.product_system(5, 7, 2)
+    assert W.terms_bytes_per_point(s2) == 8 * 35 + 64 * 5 + 32 * 7 + 32 * 35
