@@ -636,11 +636,17 @@ __device__ __forceinline__ void process_chunks(const SysView& S, uint32_t ch0, u
     // no registers to spare across it), QD, whose registers are already
     // spilled to the accumulation registers, after the owners add
     constexpr int kWhen = limbs_of(L) == 2 ? 0 : (limbs_of(L) == 1 ? 1 : 2);
-    if (kWhen == 0 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    const bool more = base + G < ch1;
+    const bool act = base + G + sg < ch1;
+    if (kWhen == 0 && more) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, act, lt, vpt, cl);
+    // D and QD: the next chunk's descriptor (scalar registers) is fetched
+    // before the barrier, so that only the records' load waits after it
+    ChunkDesc nd{};
+    if (kWhen != 0 && more && act) nd = S.chunks[uint32_t(__builtin_amdgcn_readfirstlane(int(base + G + sg)))];
     __syncthreads();
-    if (kWhen == 1 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    if (kWhen == 1 && more) load_chunk_of<L, SEG, CPL, MODE>(S, nd, act, lt, vpt, cl);
     chunk_owners<L, CPL>(cb, ce, contrib, S.max_slots, acc);
-    if (kWhen == 2 && base + G < ch1) load_chunk<L, SEG, CPL, MODE>(S, base + G + sg, base + G + sg < ch1, lt, vpt, cl);
+    if (kWhen == 2 && more) load_chunk_of<L, SEG, CPL, MODE>(S, nd, act, lt, vpt, cl);
     __syncthreads();
   }
 }
