@@ -161,8 +161,8 @@ hipError_t launch_terms_t(const EvalShape& sh, int P, const double* x, const Out
   // enough
   const int64_t quads = (sh.n_chunks + 3) / 4;
   int64_t wpp = std::max<int64_t>((quads + 7) / 8, (2048 + P - 1) / P);
-  wpp = std::max<int64_t>(1, std::min<int64_t>(wpp, quads));
-  if (int64_t(P) * wpp > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  // (and at most 2^31 - 1 in all: a workgroup then takes more chunks)
+  wpp = std::max<int64_t>(1, std::min<int64_t>({wpp, quads, 0x7fffffffLL / std::max(P, 1)}));
   hipLaunchKernelGGL(kern, dim3(unsigned(int64_t(P) * wpp)), dim3(kSub), lds, st, V, O, x,
                      int64_t(width_of(L)) * V.n, int(wpp), uint32_t(sh.n_chunks));
   return hipGetLastError();
