@@ -168,7 +168,7 @@ def test_work_model_counts_the_one_lane_schedule(k):
         assert live == W.executed_products(k, ell)
 
 
-def test_survey_count_bounds_the_schedule():
+def test_method_count_bounds_the_schedule():
     """The algorithmic count with a separate term formation (tree 3k - 5,
     common factor and coefficient, value, k partials) is at least what the
     fused schedule executes on one lane."""
