@@ -87,7 +87,8 @@ def test_wide_rows_in_column_tiles(pe, L):
     """Rows of J wider than 2048 columns (n = 4500: three tiles of 2048
     columns, one workgroup each): every row of F and J at two points against
     the oracle, and F of the F-only evaluation (one workgroup per row, F from
-    the forward products) too; the adjoint and batches refuse the system."""
+    the forward products) too; the per-monomial output of sampled monomials
+    too; the adjoint and batches refuse the system."""
     import torch
     n = 4500
     sys_ = synth.random_system((761, L), L, n_vars=n, n_polys=6, m=150, k=5, exp_lo=1, exp_hi=3)
@@ -104,6 +105,25 @@ def test_wide_rows_in_column_tiles(pe, L):
         eF2, _ = U.max_errors_rows(sys_, x[pt], F2[pt], J[pt], range(sys_.n_polys))
         U.flush(f"wide rows L={L} point {pt}: eF={eF:.2e} eJ={eJ:.2e} F-only {eF2:.2e} tol={tol:.1e}")
         assert eF <= tol and eJ <= tol and eF2 <= tol, (pt, eF, eJ, eF2)
+    # the per-monomial output of the same wide system (no column tiles:
+    # every partial goes to its input position), sampled monomials of the
+    # first and last rows against the oracle at both points
+    V, Gt = S.eval_terms(xd)
+    torch.cuda.synchronize()
+    V, Gt = V.cpu().numpy(), Gt.cpu().numpy()
+    mons = sorted({0, 1, int(sys_.poly_ptr[1]) - 1, sys_.n_monomials - 2, sys_.n_monomials - 1})
+    for pt in range(2):
+        T = O.eval_terms(sys_, x[pt], mons)
+        A = O.abs_terms(sys_, x[pt], mons)
+        worst = 0.0
+        for t in mons:
+            v, g = T[t]
+            worst = max(worst, O.rel_error(V[pt, 0, :, t], V[pt, 1, :, t], v, A[t][0]))
+            o0 = int(sys_.mon_ptr[t])
+            for r, (gr, sg) in enumerate(zip(g, A[t][1])):
+                worst = max(worst, O.rel_error(Gt[pt, 0, :, o0 + r], Gt[pt, 1, :, o0 + r], gr, sg))
+        U.flush(f"wide rows L={L} point {pt}: terms worst {worst:.2e}")
+        assert worst <= tol, (pt, worst)
     if L == 2:
         v = torch.zeros((2, 2, L, sys_.n_polys), dtype=torch.float64, device="cuda")
         with pytest.raises(pe.PolyevalError):
