@@ -45,10 +45,13 @@ BATCH_COUNT, BATCH_POINTS = 4096, 8
 # per dispatch, scaled by what the same counters read for a plain device copy
 # of known size) and FP64 instruction counts.  They hold for the kernel
 # sources they were taken with: the bench reports them only while the
-# sources match.
+# sources match.  Every counted workload is an evaluation, so the digest
+# covers the evaluation kernels' sources, their arithmetic, packing, planning
+# and launchers (the least-squares and Gauss-Newton kernels are not among
+# them).
 COUNTERS_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["eval_kernels.hpp", "mdarith.hpp", "layout.hpp", "polyeval.hip", "packer.cpp", "packer.hpp",
-                  "launch.hpp", "instances.hip", "newton_kernels.hpp"]
+                  "launch.hpp", "instances.hip"]
 
 
 def kernel_source_digest() -> str:

@@ -2,13 +2,19 @@
 // matrix [A b] with A = J(x), b = -F(x) (Sec. 3, Fig. 4 and eq. (2)), back
 // substitution R dx = y, and the update x += dx (Sec. 4).
 //
-// One workgroup per (system, point); thread j owns columns j, j + T, ... of
-// [A b].  Column k (the pivot) is staged in LDS at step k.  As in the paper's
-// delayed normalisation, the pivot column is never normalised in memory: the
+// One workgroup per (system, point); thread t owns columns t, t + T, ... of
+// [A b].  As in the paper's delayed
+// normalisation, the pivot column is never normalised in memory: the
 // projection coefficient of column j is (a_k^H a_j) / |a_k|^2 and
 // r_kj = (a_k^H a_j) / |a_k|, which is all the least-squares solve needs
-// (Q itself is not returned).  The squared norm of the next pivot is
-// accumulated by its owner while it updates that column.
+// (Q itself is not returned).  Step k first updates column k + 1 with pivot
+// k, all threads together, and stages it in LDS beside pivot k; then every
+// later column is updated with pivot k and, in the same pass over its rows,
+// its inner product with column k + 1 (the next pivot) is accumulated.  So a
+// column is read and written once per pivot instead of read twice, with the
+// arithmetic (and its order) of the plain loop: inner products summed over
+// the rows in order, the squared norm of the next pivot summed in order by
+// one thread.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -73,9 +79,11 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
   const int tid = threadIdx.x;
   const int ld = n + 1;
   const int64_t plane = int64_t(N) * ld;
-  double* colk = lds;                             // N numbers, AoS
-  double* sh = colk + size_t(N) * W;              // |a_k|^2 of the next pivot
-  double* red = sh + W;                           // T doubles for reductions
+  double* colk = lds;                             // N numbers, AoS: pivot k
+  double* coln = colk + size_t(N) * W;            // N numbers: column k + 1
+  double* sh = coln + size_t(N) * W;              // |a_k|^2 of the pivot
+  double* dpub = sh + W;                          // a_k^H a_{k+1}
+  double* red = dpub + W;                         // T doubles for reductions
   int* flag = reinterpret_cast<int*>(red + T);    // singular flag
 
   // |F|_2 from the leading limbs of b = -F
@@ -95,18 +103,30 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
   const double fnorm = sqrt(red[0]);
   __syncthreads();
 
-  // squared norm of column 0
+  // squared norm of column 0, and column 0 staged as the first pivot
   if (tid == 0) {
     RL s2 = r_zero<limbs_of(L)>();
     for (int i = 0; i < N; ++i) s2 = r_add(s2, c_norm2(load_planar<L>(A, plane, int64_t(i) * ld)));
     r_store_aos(sh, s2);
   }
+  for (int i = tid; i < N; i += T) store_aos(colk + size_t(i) * W, load_planar<L>(A, plane, int64_t(i) * ld));
+  __syncthreads();
+  // inner products of the pivot with the thread's columns j >= 1, kept
+  // (unscaled) in R's row 0 until step 0 scales them; the one with column 1
+  // also goes to LDS (dpub) for the cooperative update
+  for (int j = tid; j <= n; j += T) {
+    if (j < 1) continue;
+    C<L> d = c_zero<L>();
+    for (int i = 0; i < N; ++i)
+      d = c_add(d, c_mul_conj_a(load_aos<L>(colk + size_t(i) * W), load_planar<L>(A, plane, int64_t(i) * ld + j)));
+    store_aos(Rm + size_t(j) * W, d);
+    if (j == 1) store_aos(dpub, d);
+  }
+  __syncthreads();
   double rmax = 0.0;
   const double uL = level_unit<L>();
 
   for (int k = 0; k < n; ++k) {
-    for (int i = tid; i < N; i += T) store_aos(colk + size_t(i) * W, load_planar<L>(A, plane, int64_t(i) * ld + k));
-    __syncthreads();
     const RL nk = r_load_aos<limbs_of(L)>(sh);
     const RL rkk = r_sqrt(nk);
     rmax = fmax(rmax, rkk.x[0]);
@@ -116,25 +136,49 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
     }
     const RL inv_n = r_recip(nk);
     const RL inv_r = r_recip(rkk);
-    if (tid == 0) store_aos(Rm + (size_t(k) * ld + k) * W, c_from_r<L>(rkk));
-    __syncthreads();  // everyone has read sh before it is overwritten below
-    for (int j = k + 1 + tid; j <= n; j += T) {
-      C<L> dot = c_zero<L>();
-      for (int i = 0; i < N; ++i)
-        dot = c_add(dot, c_mul_conj_a(load_aos<L>(colk + size_t(i) * W), load_planar<L>(A, plane, int64_t(i) * ld + j)));
-      store_aos(Rm + (size_t(k) * ld + j) * W, c_mul_r(dot, inv_r));
-      const C<L> cr = c_neg(c_mul_r(dot, inv_n));
-      const bool next = (j == k + 1);
+    // column k + 1 (the next pivot; the right-hand side when k + 1 = n)
+    // updated with pivot k by all threads and staged in LDS
+    const C<L> d1 = load_aos<L>(dpub);
+    const C<L> cr1 = c_neg(c_mul_r(d1, inv_n));
+    for (int i = tid; i < N; i += T) {
+      C<L> a = load_planar<L>(A, plane, int64_t(i) * ld + k + 1);
+      a = c_add(a, c_mul(cr1, load_aos<L>(colk + size_t(i) * W)));
+      store_planar(A, plane, int64_t(i) * ld + k + 1, a);
+      store_aos(coln + size_t(i) * W, a);
+    }
+    if (tid == 0) {
+      store_aos(Rm + (size_t(k) * ld + k) * W, c_from_r<L>(rkk));
+      store_aos(Rm + (size_t(k) * ld + k + 1) * W, c_mul_r(d1, inv_r));
+    }
+    __syncthreads();  // column k + 1 staged; sh and dpub read by everyone
+    if (tid == 0) {
       RL s2 = r_zero<limbs_of(L)>();
+      for (int i = 0; i < N; ++i) s2 = r_add(s2, c_norm2(load_aos<L>(coln + size_t(i) * W)));
+      r_store_aos(sh, s2);
+    }
+    // columns k + 2 .. n: update with pivot k (whose inner product with the
+    // column the previous step left unscaled in R's row k) and, in the same
+    // pass, the inner product with column k + 1, left unscaled in row k + 1
+    for (int j = tid; j <= n; j += T) {
+      if (j < k + 2) continue;
+      double* rkj = Rm + (size_t(k) * ld + j) * W;
+      const C<L> d = load_aos<L>(rkj);
+      store_aos(rkj, c_mul_r(d, inv_r));
+      const C<L> cr = c_neg(c_mul_r(d, inv_n));
+      C<L> dn = c_zero<L>();
       for (int i = 0; i < N; ++i) {
         C<L> a = load_planar<L>(A, plane, int64_t(i) * ld + j);
         a = c_add(a, c_mul(cr, load_aos<L>(colk + size_t(i) * W)));
         store_planar(A, plane, int64_t(i) * ld + j, a);
-        if (next) s2 = r_add(s2, c_norm2(a));
+        dn = c_add(dn, c_mul_conj_a(load_aos<L>(coln + size_t(i) * W), a));
       }
-      if (next) r_store_aos(sh, s2);
+      store_aos(Rm + (size_t(k + 1) * ld + j) * W, dn);
+      if (j == k + 2) store_aos(dpub, dn);
     }
     __syncthreads();
+    double* t = colk;
+    colk = coln;
+    coln = t;
   }
   __syncthreads();
   const bool singular = *flag != 0;
@@ -237,7 +281,8 @@ __global__ void rhs_shift_kernel(double* __restrict__ W, int64_t w_pt, int64_t p
 
 template <int L>
 __host__ __device__ inline size_t mgs_lds_bytes(int N) {
-  return size_t(N) * width_of(L) * sizeof(double) + width_of(L) * sizeof(double) + kMgsThreads * sizeof(double) + 16;
+  return 2 * size_t(N) * width_of(L) * sizeof(double) + 2 * width_of(L) * sizeof(double) +
+         kMgsThreads * sizeof(double) + 16;
 }
 
 }  // namespace pe
