@@ -12,9 +12,10 @@
 // later column is updated with pivot k and, in the same pass over its rows,
 // its inner product with column k + 1 (the next pivot) is accumulated.  So a
 // column is read and written once per pivot instead of read twice, with the
-// arithmetic (and its order) of the plain loop: inner products summed over
-// the rows in order, the squared norm of the next pivot summed in order by
-// one thread.
+// arithmetic (and its order) of the plain loop for the inner products
+// (summed over the rows in order); the squared norm of the next pivot is a
+// workgroup sum (each thread's rows, then an XOR butterfly per wavefront,
+// then the wavefronts in order).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -84,7 +85,8 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
   double* sh = coln + size_t(N) * W;              // |a_k|^2 of the pivot
   double* dpub = sh + W;                          // a_k^H a_{k+1}
   double* red = dpub + W;                         // T doubles for reductions
-  int* flag = reinterpret_cast<int*>(red + T);    // singular flag
+  double* wsum = red + T;                         // T / 64 wavefront sums of limbs_of(L) doubles
+  int* flag = reinterpret_cast<int*>(wsum + (T / 64) * 4);  // singular flag
 
   // |F|_2 from the leading limbs of b = -F
   double fs = 0.0;
@@ -140,21 +142,32 @@ __device__ void mgs_solve_point(int N, int n, double* __restrict__ A, double* __
     // updated with pivot k by all threads and staged in LDS
     const C<L> d1 = load_aos<L>(dpub);
     const C<L> cr1 = c_neg(c_mul_r(d1, inv_n));
+    RL s2 = r_zero<limbs_of(L)>();  // the thread's rows of |a_{k+1}|^2
     for (int i = tid; i < N; i += T) {
       C<L> a = load_planar<L>(A, plane, int64_t(i) * ld + k + 1);
       a = c_add(a, c_mul(cr1, load_aos<L>(colk + size_t(i) * W)));
       store_planar(A, plane, int64_t(i) * ld + k + 1, a);
       store_aos(coln + size_t(i) * W, a);
+      s2 = r_add(s2, c_norm2(a));
     }
+    // wavefront sums by an XOR butterfly, then the wavefronts' in order
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      RL o;
+#pragma unroll
+      for (int l = 0; l < limbs_of(L); ++l) o.x[l] = __shfl_xor(s2.x[l], m);
+      s2 = r_add(s2, o);
+    }
+    if ((tid & 63) == 0) r_store_aos(wsum + (tid / 64) * 4, s2);
     if (tid == 0) {
       store_aos(Rm + (size_t(k) * ld + k) * W, c_from_r<L>(rkk));
       store_aos(Rm + (size_t(k) * ld + k + 1) * W, c_mul_r(d1, inv_r));
     }
     __syncthreads();  // column k + 1 staged; sh and dpub read by everyone
     if (tid == 0) {
-      RL s2 = r_zero<limbs_of(L)>();
-      for (int i = 0; i < N; ++i) s2 = r_add(s2, c_norm2(load_aos<L>(coln + size_t(i) * W)));
-      r_store_aos(sh, s2);
+      RL t2 = r_load_aos<limbs_of(L)>(wsum);
+      for (int w = 1; w < T / 64; ++w) t2 = r_add(t2, r_load_aos<limbs_of(L)>(wsum + w * 4));
+      r_store_aos(sh, t2);
     }
     // columns k + 2 .. n: update with pivot k (whose inner product with the
     // column the previous step left unscaled in R's row k) and, in the same
@@ -282,7 +295,7 @@ __global__ void rhs_shift_kernel(double* __restrict__ W, int64_t w_pt, int64_t p
 template <int L>
 __host__ __device__ inline size_t mgs_lds_bytes(int N) {
   return 2 * size_t(N) * width_of(L) * sizeof(double) + 2 * width_of(L) * sizeof(double) +
-         kMgsThreads * sizeof(double) + 16;
+         kMgsThreads * sizeof(double) + (kMgsThreads / 64) * 4 * sizeof(double) + 16;
 }
 
 }  // namespace pe
